@@ -1,0 +1,239 @@
+"""Benchmark of the domain-wall Dslash and CG on one MI355X.
+
+Prints ONE JSON line. The headline value is the FP32 Mobius domain-wall
+operator D (b=1.5, c=0.5, M5=1.8, mf=0.01) applied to a full 32^4 x Ls=16
+lattice with Haar-random links and a Gaussian spinor (synthetic, seeded),
+in GFlop/s with the 1320-flops-per-5D-site convention of the paper's Table 3.
+A "step" is one application of D to the whole 5D lattice, inputs resident in
+HBM. Alongside it: HBM roofline fraction of that kernel (algorithmic bytes),
+the split-plane (RRII) and interleaved (RIRI) layouts side by side, the
+even-odd hop, FP64 / FP16 / BF16 variants, mixed-precision and plain FP64 CG
+solves/s on 24^4 x 16 with smoothed links, and the FP64 CPU oracle timed on
+the host cores on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solver] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+FLOPS_PER_SITE = 1320        # Table 3 (real flops per 5D site per hop)
+MOBIUS = dict(M5=1.8, mf=0.01, b=1.5, c=0.5)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_launches(fn, steps, warmup, torch):
+    """Average launch duration (ms) from HIP events on the launch stream."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        fn()
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def algorithmic_bytes_per_site(prec_bytes, Ls, eo):
+    """Each input and output spinor touched once (24 reals each) plus the
+    links of a 4D site shared by its Ls slices: 72/Ls reals per 5D site for
+    the full operator, 144/Ls when only one parity is written (each output
+    site still needs all 8 of its links)."""
+    links = (144.0 if eo else 72.0) / Ls
+    return (24 + 24 + links) * prec_bytes
+
+
+def dslash_bench(args, torch, q, I):
+    L, Ls = (32, 32, 32, 32), 16
+    t0 = time.time()
+    U = I.gauge_field(L, "haar", 2000, dtype=np.complex64)
+    psi = I.gaussian_spinor(L, Ls, 2001, dtype=np.complex64)
+    log(f"inputs generated in {time.time() - t0:.1f}s")
+    D = q.Dirac(L, Ls, **MOBIUS)
+    D.set_gauge(torch.from_numpy(U))
+    del U
+    psi_d = torch.from_numpy(psi).cuda()
+    del psi
+    sites = D.V * Ls
+    res = {}
+    variants = [("f32", q.QDWF_F32, q.QDWF_RIRI), ("f32", q.QDWF_F32, q.QDWF_RRII),
+                ("f64", q.QDWF_F64, q.QDWF_RIRI), ("f16", q.QDWF_F16, q.QDWF_RIRI),
+                ("bf16", q.QDWF_BF16, q.QDWF_RIRI)]
+    for name, prec, layout in variants:
+        lname = "riri" if layout == q.QDWF_RIRI else "rrii"
+        if args.variants and f"{name}_{lname}" not in args.variants.split(","):
+            continue
+        fin = D.field(prec, q.QDWF_FULL, zero=False)
+        q.qdwf_pack_spinor(D.ctx, fin, prec, layout, psi_d, q.QDWF_FULL)
+        fout = D.field(prec, q.QDWF_FULL, zero=False)
+        pb = fin.element_size()
+        fn = lambda: q.qdwf_apply_D(D.ctx, fout, fin, 0, prec, layout)
+        ms = time_launches(fn, args.steps, args.warmup, torch)
+        gflops = FLOPS_PER_SITE * sites / (ms * 1e-3) / 1e9
+        gbs = algorithmic_bytes_per_site(pb, Ls, False) * sites / (ms * 1e-3) / 1e9
+        key = f"D_{name}_{lname}"
+        res[key] = {"ms": ms, "gflops": gflops, "algo_GBs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
+        log(key, res[key])
+        # D^dag and the even-odd hop for the FP32 variants
+        if prec == q.QDWF_F32:
+            fn = lambda: q.qdwf_apply_D(D.ctx, fout, fin, 1, prec, layout)
+            ms = time_launches(fn, max(args.steps // 2, 3), 2, torch)
+            res[f"Ddag_{name}_{lname}"] = {
+                "ms": ms, "gflops": FLOPS_PER_SITE * sites / (ms * 1e-3) / 1e9,
+                "algo_GBs": algorithmic_bytes_per_site(pb, Ls, False) * sites / (ms * 1e-3) / 1e9}
+            half_in = fin[: fin.numel() // 2]
+            half_out = fout[: fout.numel() // 2]
+            fn = lambda: q.qdwf_apply_Deo(D.ctx, half_out, half_in, q.QDWF_ODD, 0, prec, layout)
+            ms = time_launches(fn, max(args.steps // 2, 3), 2, torch)
+            hs = sites // 2
+            res[f"Deo_{name}_{lname}"] = {
+                "ms": ms, "gflops": FLOPS_PER_SITE * hs / (ms * 1e-3) / 1e9,
+                "algo_GBs": algorithmic_bytes_per_site(pb, Ls, True) * hs / (ms * 1e-3) / 1e9}
+            log(f"Ddag/Deo {lname}", res[f"Ddag_{name}_{lname}"], res[f"Deo_{name}_{lname}"])
+        del fin, fout
+        torch.cuda.empty_cache()
+    D.close()
+    return res, sites
+
+
+def copy_probe(torch, nbytes=2 << 30, steps=20):
+    """Attainable HBM bandwidth: a plain device-to-device copy of 2 GiB
+    (read + write counted), timed with HIP events."""
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    ms = time_launches(lambda: dst.copy_(src), steps, 3, torch)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * nbytes, "ms": ms, "GBs": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
+def solver_bench(args, torch, q, I):
+    """Plain FP64 CG vs mixed-precision reliable-update CG on 24^4 x 16."""
+    L, Ls = (24, 24, 24, 24), 16
+    U = I.gauge_field(L, "smooth", 3000, eps=0.3)
+    b = I.gaussian_spinor(L, Ls, 3001)
+    D = q.Dirac(L, Ls, **MOBIUS)
+    D.set_gauge(U)
+    bo = D.pack(b, q.QDWF_F64, q.QDWF_RIRI, q.QDWF_ODD)
+    del b, U
+    out = {}
+    for name, inner in (("f64", q.QDWF_F64), ("f32", q.QDWF_F32), ("f16", q.QDWF_F16),
+                        ("bf16", q.QDWF_BF16)):
+        ws = D.workspace(q.QDWF_OP_SOLVE, inner)
+        x = D.field(q.QDWF_F64, q.QDWF_ODD)
+        prm = q.solve_params(inner_prec=inner, layout=q.QDWF_RIRI, tol=1e-10, check_every=8,
+                             use_graph=1)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        rc, st = q.qdwf_solve(D.ctx, x, bo, 1, prm, ws)
+        dt = time.time() - t0
+        out[name] = {"rc": rc, "seconds": dt, "solves_per_s": 1.0 / dt,
+                     "iterations": st.iterations, "reliable_updates": st.reliable_updates,
+                     "true_residual": st.true_residual,
+                     "gflops": st.flops / dt / 1e9}
+        log("solve", name, out[name])
+        del ws, x
+        torch.cuda.empty_cache()
+    D.close()
+    return out
+
+
+def cpu_baseline():
+    """FP64 oracle (plain C++ loops, OpenMP) applying the same operator to a
+    16^4 x 16 lattice: 1/16 of the 32^4 x 16 workload's 5D volume."""
+    from oracle import cpu
+    from paper_2112_01852_amd import inputs as I
+    cpu.build(force=False)
+    L, Ls = (16, 16, 16, 16), 16
+    a = cpu.Action(L=L, Ls=Ls, **MOBIUS)
+    U = I.gauge_field(L, "haar", 2000)
+    psi = I.gaussian_spinor(L, Ls, 2001)
+    t0 = time.time()
+    cpu.dwf(a, U, psi)
+    dt = time.time() - t0
+    sites = a.V * Ls
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count()
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    return {"value": FLOPS_PER_SITE * sites / dt / 1e9, "unit": "GFlop/s", "cores": min(cores, threads),
+            "kind": "oracle", "seconds": dt,
+            "sample": "FP64 oracle D_dwf (Mobius b=1.5 c=0.5) on a 16^4 x Ls16 lattice, "
+                      "1/16 of the 32^4 x 16 5D volume; GFlop/s with 1320 flops per 5D site"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-solver", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--variants", default="",
+                    help="comma list of Dslash variants to time (default all), e.g. f32_riri")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2112_01852_amd import qdwf as q
+    from paper_2112_01852_amd import inputs as I
+    q.lib()
+    probe = copy_probe(torch)
+    log("copy probe", probe)
+    dres, sites = dslash_bench(args, torch, q, I)
+    cands = [k for k in ("D_f32_riri", "D_f32_rrii") if k in dres]
+    best = min(cands, key=lambda k: dres[k]["ms"])
+    best_layout = best.split("_")[-1]
+    head = dres[best]
+    solver = None if args.no_solver else solver_bench(args, torch, q, I)
+    cpub = None if args.no_cpu else cpu_baseline()
+    line = {
+        "metric": "Dslash GFlop/s+HBM GB/s (32^4xLs16); mixed-prec CG solves/s, p50/p99 latency",
+        "value": head["gflops"],
+        "unit": "GFlop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "Mobius domain-wall D (b=1.5, c=0.5, M5=1.8, mf=0.01), FP32, "
+                               "full 32^4 x Ls16 lattice, Haar SU(3) links, Gaussian spinor",
+                   "layout": best_layout, "lattice": [32, 32, 32, 32], "Ls": 16,
+                   "sites_5d": sites, "parallelism": "single GPU"},
+        "hbm_GBs_algorithmic": head["algo_GBs"],
+        "roofline": {"bound": "hbm", "achieved": head["algo_GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": head["algo_GBs"] / HBM_PEAK_GBS, "traffic": None},
+        "attainable_hbm": probe,
+        "dslash": dres,
+        "solver_24x24x24x24x16": solver,
+        "cpu_baseline": cpub,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,231 @@
+/*
+ * qdwf -- domain-wall fermion Dirac operator and Krylov solver for MI355X (gfx950).
+ *
+ * C ABI of libqdwf.so. Plain pointers and sizes only; every device buffer is
+ * owned by the caller unless stated otherwise. All calls return a status code
+ * (QDWF_OK = 0); on failure qdwf_last_error() gives a thread-local message.
+ * Argument checks happen before any device work, so a call that returns
+ * QDWF_EINVAL has launched nothing. No exception or abort crosses the ABI.
+ *
+ * What is computed (the paper, arXiv 2112.01852, Sections 4.1-4.3, names the
+ * Domain Wall kernel -- the 4D Wilson hopping term with SU(3) link multiplies
+ * applied on every slice of the fifth dimension -- as the performance-relevant
+ * part of the domain-wall operator, and counts 1320 real flops per 5D site for
+ * it in Table 3; the operator itself is not written out in the paper, so the
+ * standard conventions below are the definitions used):
+ *
+ *   lattice     L = (Lx, Ly, Lz, Lt), all even; lex = ((t*Lz+z)*Ly+y)*Lx+x;
+ *               parity = (x+y+z+t) mod 2.
+ *   gamma       DeGrand-Rossi chiral basis, gamma5 = diag(1,1,-1,-1);
+ *               P+ keeps spins 0,1 and P- keeps spins 2,3.
+ *   hop         (D_h psi)(x,s) = sum_mu [ (1-g_mu) U_mu(x) psi(x+mu,s)
+ *                                       + (1+g_mu) U_mu(x-mu)^dag psi(x-mu,s) ],
+ *               each hop across the mu boundary multiplied by bc[mu].
+ *   Wilson      D_W = (4 - M5) - D_h / 2.
+ *   5th dim     (S_u psi)_s = psi_{s+1}, row Ls-1 takes -mf psi_0;
+ *               (S_d psi)_s = psi_{s-1}, row 0 takes -mf psi_{Ls-1};
+ *               C = P- S_u + P+ S_d; A = b + c C; B = 1 - C.
+ *   operator    D = D_W A + B (Shamir: b = 1, c = 0); D^dag = A^dag D_W^dag + B^dag.
+ *   even-odd    M_ee = M_oo = alpha + beta C, alpha = b(4-M5)+1, beta = c(4-M5)-1;
+ *               M_pq = -1/2 D_h^{pq} A (p != q);
+ *               M_pc = M_oo - M_oe M_ee^-1 M_eo on odd sites.
+ *   flops       1320 per 5D output site per hop application (Table 3),
+ *               times the number of right-hand sides; 5D-local work is not counted.
+ *
+ * Canonical (caller-facing) layouts, row-major, interleaved complex:
+ *   gauge   U[mu][t][z][y][x][a][b]                 (mu = x, y, z, t)
+ *   spinor  psi[rhs][s][t][z][y][x][spin][colour]
+ * Internal spinor fields (what the operators take) are produced by
+ * qdwf_pack_spinor. A half field holds one parity: (V/2)*Ls 5D sites, site
+ * index j = i*Ls + s, 24 reals per site, where i numbers the 4D sites of that
+ * parity in the library's traversal order (8 slabs along z, one per XCD, each
+ * in (t, z, y, x) order; qdwf_geometry_tables exports it). A full field is the even half
+ * followed by the odd half. nrhs fields of the same kind are stored back to
+ * back. Two layouts of the 24 reals of a site exist (Section 4.3 compares the
+ * same two choices for SVE registers):
+ *   QDWF_RIRI  interleaved complex: field[j][spin][colour][re,im]
+ *   QDWF_RRII  split planes:        field[re/im][spin][colour][j] per parity half
+ * Precisions give the storage type of a real; arithmetic is FP64 for QDWF_F64
+ * and FP32 for the others (FP16/BF16 are storage only, rounded to nearest even).
+ */
+#ifndef QDWF_H
+#define QDWF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ----------------------------------------------------- */
+#define QDWF_OK        0
+#define QDWF_EINVAL    1   /* bad argument; nothing was launched */
+#define QDWF_ENOMEM    2   /* a library-owned allocation failed (create / set_gauge only) */
+#define QDWF_EDEVICE   3   /* a HIP call failed; message carries hipGetErrorString */
+#define QDWF_ENOTCONV  4   /* solver hit max_iter before reaching tol (stats are filled) */
+#define QDWF_ENAN      5   /* solver met a NaN or Inf */
+#define QDWF_EBUSY     6   /* pool request not finished yet */
+
+/* ---- enums ------------------------------------------------------------ */
+#define QDWF_F64   0
+#define QDWF_F32   1
+#define QDWF_F16   2
+#define QDWF_BF16  3
+
+#define QDWF_RRII  0
+#define QDWF_RIRI  1
+
+#define QDWF_EVEN  0
+#define QDWF_ODD   1
+#define QDWF_FULL  2
+
+/* 5D-local operator selectors for qdwf_apply_Mee */
+#define QDWF_MEE_FWD   0   /* M_ee                 */
+#define QDWF_MEE_INV   1   /* M_ee^-1              */
+
+/* solver systems */
+#define QDWF_SYS_NORMAL_PC 0   /* M_pc^dag M_pc x = b on odd half fields      */
+#define QDWF_SYS_FULL      1   /* D x = b on full fields (Schur + normal eq.) */
+
+/* workspace selectors for qdwf_workspace_bytes */
+#define QDWF_OP_MPC     0
+#define QDWF_OP_MDAGM   1
+#define QDWF_OP_SOLVE   2
+#define QDWF_OP_REDUCE  3
+
+/* ---- types ------------------------------------------------------------ */
+typedef struct {
+  int32_t L[4];     /* extents x, y, z, t; each even and >= 2                 */
+  int32_t Ls;       /* fifth-dimension extent, 2 <= Ls <= 64                  */
+  int32_t bc[4];    /* +1 periodic, -1 antiperiodic per direction            */
+  double M5;        /* domain-wall height                                    */
+  double mf;        /* quark mass (wall coupling -mf)                        */
+  double b, c;      /* Mobius coefficients (b != 0); Shamir is b = 1, c = 0   */
+} qdwf_action;
+
+typedef struct qdwf_ctx qdwf_ctx;
+
+typedef struct {
+  int32_t system;       /* QDWF_SYS_NORMAL_PC or QDWF_SYS_FULL                      */
+  int32_t inner_prec;   /* precision of the inner Dslash: QDWF_F64 = plain FP64 CG; */
+                        /* F32/F16/BF16 = reliable-update mixed-precision CG        */
+  int32_t layout;       /* layout of x, b and every internal vector                 */
+  int32_t max_iter;     /* total inner iterations allowed (default 20000 if <= 0)   */
+  double tol;           /* target relative FP64 true residual |b-Ax|/|b|            */
+  double delta;         /* reliable-update threshold (default 0.1 if <= 0)          */
+  int32_t x0_is_guess;  /* nonzero: x holds an initial guess; else x0 = 0          */
+  int32_t check_every;  /* iterations between host convergence checks (>= 1)        */
+  int32_t use_graph;    /* nonzero: replay the inner iterations as a HIP graph      */
+} qdwf_solve_params;
+
+typedef struct {
+  int32_t iterations;        /* inner CG iterations (max over right-hand sides)   */
+  int32_t reliable_updates;  /* FP64 true-residual recomputations                 */
+  int32_t converged;         /* number of right-hand sides that reached tol      */
+  int32_t restarts;          /* reserved                                          */
+  double true_residual;      /* max over rhs of |b - A x| / |b| in FP64 (system solved) */
+  double full_residual;      /* QDWF_SYS_FULL: max over rhs of |b - D x| / |b|    */
+  double seconds;            /* wall time of the call                              */
+  int64_t flops;             /* hop flops executed (1320 convention)               */
+} qdwf_solve_stats;
+
+/* ---- errors ----------------------------------------------------------- */
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* qdwf_last_error(void);
+
+/* ---- lifecycle -------------------------------------------------------- */
+/* Validates the action and, on `device`, allocates the library-owned
+ * neighbour tables (int32 [2][8][V/2]) and 5D-local matrices. Links are added
+ * by qdwf_set_gauge. Distinct contexts are independent; one context must not
+ * be used from two threads at once. */
+int qdwf_create(const qdwf_action* act, int device, qdwf_ctx** out);
+int qdwf_destroy(qdwf_ctx* ctx);
+
+/* Packs the canonical gauge field U (device pointer; complex128 when
+ * canon_prec = QDWF_F64, complex64 when QDWF_F32) into library-owned link
+ * arrays in every precision, per parity, with the boundary factors bc folded
+ * into the links. Stream-ordered on `stream` (a hipStream_t, NULL = default). */
+int qdwf_set_gauge(qdwf_ctx* ctx, const void* U, int canon_prec, void* stream);
+
+/* Number of reals in one right-hand side of an internal field of `subset`
+ * (QDWF_EVEN / QDWF_ODD half field, QDWF_FULL full field). */
+size_t qdwf_field_reals(const qdwf_ctx* ctx, int subset);
+
+/* ---- layout conversion ------------------------------------------------ */
+/* Canonical spinor (device, complex128 if src_prec = QDWF_F64, complex64 if
+ * QDWF_F32; nrhs fields back to back) -> internal field of `subset` in
+ * (prec, layout). Down-conversion rounds to nearest even. */
+int qdwf_pack_spinor(qdwf_ctx* ctx, void* dst, int prec, int layout, const void* src,
+                     int src_prec, int subset, int nrhs, void* stream);
+/* Internal -> canonical. For a half field only the sites of that parity are
+ * written; the others are left untouched. */
+int qdwf_unpack_spinor(qdwf_ctx* ctx, void* dst, int dst_prec, const void* src, int prec,
+                       int layout, int subset, int nrhs, void* stream);
+
+/* ---- operators (all asynchronous on `stream`; out must not alias in) --- */
+/* Full 5D domain-wall operator: out = D in (dagger = 0) or D^dag in
+ * (dagger = 1). in, out: full fields, nrhs right-hand sides. */
+int qdwf_apply_D(qdwf_ctx* ctx, void* out, const void* in, int dagger, int prec, int layout,
+                 int nrhs, void* stream);
+
+/* 4D-local block on `subset` fields: which = QDWF_MEE_FWD gives M_ee,
+ * QDWF_MEE_INV gives M_ee^-1; dagger = 1 gives the adjoint. M_ee = M_oo, so
+ * the same call serves either parity. out may equal in. */
+int qdwf_apply_Mee(qdwf_ctx* ctx, void* out, const void* in, int subset, int dagger, int which,
+                   int prec, int layout, int nrhs, void* stream);
+
+/* Off-diagonal block into parity out_parity from half field of parity
+ * q = 1 - out_parity: dagger = 0 gives M_{p,q} in = -1/2 D_h A in;
+ * dagger = 1 gives (M_{q,p})^dag in = -1/2 A^dag D_h^dag in. */
+int qdwf_apply_Deo(qdwf_ctx* ctx, void* out, const void* in, int out_parity, int dagger,
+                   int prec, int layout, int nrhs, void* stream);
+
+/* Schur complement on odd half fields: M_pc in (dagger = 0) or M_pc^dag in.
+ * ws: qdwf_workspace_bytes(ctx, QDWF_OP_MPC, prec, nrhs) bytes of device memory. */
+int qdwf_apply_Mpc(qdwf_ctx* ctx, void* out, const void* in, int dagger, int prec, int layout,
+                   int nrhs, void* ws, void* stream);
+
+/* Normal operator on odd half fields: out = M_pc^dag M_pc in.
+ * ws: qdwf_workspace_bytes(ctx, QDWF_OP_MDAGM, prec, nrhs) bytes. */
+int qdwf_apply_MdagM(qdwf_ctx* ctx, void* out, const void* in, int prec, int layout, int nrhs,
+                     void* ws, void* stream);
+
+/* Device workspace size in bytes for an operation (see QDWF_OP_*). */
+size_t qdwf_workspace_bytes(const qdwf_ctx* ctx, int op, int prec, int nrhs);
+
+/* ---- reductions ------------------------------------------------------- */
+/* Per right-hand side r: out[2r] = Re <x_r, y_r>, out[2r+1] = Im <x_r, y_r>,
+ * accumulated in FP64 with a fixed reduction order (bitwise reproducible for
+ * a given field size). x, y: fields of `subset`, same (prec, layout). out is a
+ * host array of 2*nrhs doubles; the call synchronises `stream`.
+ * ws: qdwf_workspace_bytes(ctx, QDWF_OP_REDUCE, prec, nrhs) bytes. */
+int qdwf_dot(qdwf_ctx* ctx, double* out, const void* x, const void* y, int subset, int prec,
+             int layout, int nrhs, void* ws, void* stream);
+
+/* ---- solver ----------------------------------------------------------- */
+/* Solves for nrhs right-hand sides at once (links loaded once per tile for
+ * all of them). x, b are FP64 fields in params->layout: odd half fields for
+ * QDWF_SYS_NORMAL_PC, full fields for QDWF_SYS_FULL. inner_prec = QDWF_F64
+ * runs plain FP64 CG; any other value runs CG with that inner precision and
+ * FP64 reliable updates (true residual recomputed in FP64; x accumulated in
+ * FP64). Convergence is decided only on the FP64 true residual <= tol.
+ * ws: qdwf_workspace_bytes(ctx, QDWF_OP_SOLVE, inner_prec, nrhs) bytes.
+ * Synchronises `stream` before returning; stats may be NULL.
+ * Returns QDWF_ENOTCONV if max_iter is reached, QDWF_ENAN on NaN/Inf. */
+int qdwf_solve(qdwf_ctx* ctx, void* x, const void* b, int nrhs, const qdwf_solve_params* params,
+               qdwf_solve_stats* stats, void* ws, void* stream);
+
+/* ---- geometry (tests) ------------------------------------------------- */
+/* Copies the tables the kernels use into host buffers: cb_of_lex[V] (int32:
+ * the internal index i of each lex site within its parity), nbr[2][V/2][8]
+ * (int32: internal index of the neighbour, in the opposite parity, in
+ * directions +x,+y,+z,+t,-x,-y,-z,-t) and sign[2][V/2][8] (int8 boundary
+ * factor of the hop). Any pointer may be NULL. Synchronous. */
+int qdwf_geometry_tables(qdwf_ctx* ctx, int32_t* cb_of_lex, int32_t* nbr, int8_t* sign);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QDWF_H */

@@ -1,0 +1,484 @@
+// C ABI of libqdwf (declared in include/qdwf.h): argument validation, context
+// lifecycle and dispatch to the HIP kernels. Nothing here allocates device
+// memory outside qdwf_create / qdwf_set_gauge.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "common.h"
+#include "solver.h"
+
+namespace qdwf {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+int fail(int code, const char* fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+std::vector<double> build_local_matrices(const qdwf_action& a);
+
+}  // namespace qdwf
+
+using namespace qdwf;
+
+namespace {
+
+inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(dev) == hipSuccess) ok = true;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+#define CTX_CHECK(ctx)                                                    \
+  do {                                                                    \
+    if (!(ctx)) return fail(QDWF_EINVAL, "null context");                 \
+  } while (0)
+
+int check_prec(int prec) {
+  if (prec < QDWF_F64 || prec > QDWF_BF16) return fail(QDWF_EINVAL, "unknown precision %d", prec);
+  return QDWF_OK;
+}
+int check_layout(int layout) {
+  if (layout != QDWF_RRII && layout != QDWF_RIRI) return fail(QDWF_EINVAL, "unknown layout %d", layout);
+  return QDWF_OK;
+}
+int check_nrhs(int nrhs) {
+  if (nrhs < 1 || nrhs > 4096) return fail(QDWF_EINVAL, "nrhs %d out of range [1, 4096]", nrhs);
+  return QDWF_OK;
+}
+int check_ptr(const void* p, const char* what) {
+  if (!p) return fail(QDWF_EINVAL, "%s is NULL", what);
+  return QDWF_OK;
+}
+int check_gauge(const qdwf_ctx* ctx) {
+  if (!ctx->gauge_set) return fail(QDWF_EINVAL, "gauge field not set (call qdwf_set_gauge first)");
+  return QDWF_OK;
+}
+
+#define TRY(x)                 \
+  do {                         \
+    int rc_ = (x);             \
+    if (rc_) return rc_;       \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* qdwf_last_error(void) { return g_err.c_str(); }
+
+int qdwf_create(const qdwf_action* act, int device, qdwf_ctx** out) {
+  if (!act || !out) return fail(QDWF_EINVAL, "null argument");
+  *out = nullptr;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (act->L[mu] < 2 || (act->L[mu] & 1))
+      return fail(QDWF_EINVAL, "L[%d] = %d must be even and >= 2", mu, act->L[mu]);
+    if (act->bc[mu] != 1 && act->bc[mu] != -1)
+      return fail(QDWF_EINVAL, "bc[%d] = %d must be +1 or -1", mu, act->bc[mu]);
+  }
+  if (act->Ls < 2 || act->Ls > 64) return fail(QDWF_EINVAL, "Ls = %d must be in [2, 64]", act->Ls);
+  const double V = (double)act->L[0] * act->L[1] * act->L[2] * act->L[3];
+  if (V * act->Ls / 2 * 24 > 9.0e18 || V > 2.0e9) return fail(QDWF_EINVAL, "lattice too large");
+  if (!(std::fabs(act->b) > 0.0) || !std::isfinite(act->b))
+    return fail(QDWF_EINVAL, "Mobius b = %g must be finite and nonzero", act->b);
+  const double al = act->b * (4.0 - act->M5) + 1.0;
+  if (!std::isfinite(al) || al == 0.0 || !std::isfinite(act->mf) || !std::isfinite(act->c))
+    return fail(QDWF_EINVAL, "degenerate action: alpha = b(4-M5)+1 = %g", al);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(QDWF_EINVAL, "device %d not available (%d devices)", device, ndev);
+  DeviceGuard dg(device);
+  if (!dg.ok) return fail(QDWF_EDEVICE, "hipSetDevice(%d) failed", device);
+
+  qdwf_ctx* c = new (std::nothrow) qdwf_ctx();
+  if (!c) return fail(QDWF_ENOMEM, "host allocation failed");
+  c->act = *act;
+  c->device = device;
+  Geom& g = c->g;
+  for (int mu = 0; mu < 4; ++mu) g.L[mu] = act->L[mu];
+  g.Ls = act->Ls;
+  g.V = act->L[0] * act->L[1] * act->L[2] * act->L[3];
+  g.Vh = g.V / 2;
+  g.n5h = (long)g.Vh * g.Ls;
+
+  // Internal site order of each parity. The lattice is cut into 8 slabs
+  // along z, one per XCD (blocks of consecutive internal sites reach the XCDs
+  // in contiguous ranges); inside a slab, (x, y, z) tiles of tx * ty * tz
+  // sites are swept along t. The sites a XCD works on at any moment then form
+  // a compact 4D region whose neighbours are still in its L2, and all XCDs
+  // advance through t together, so t-neighbours shared across XCDs meet in the
+  // last-level cache. Tile sizes: QDWF_TILE="tx,ty,tz" overrides the default.
+  const int* L = g.L;
+  int tile[3] = {std::min(L[0], 16), std::min(L[1], 4), std::max(1, L[2] / 8)};
+  if (const char* e = std::getenv("QDWF_TILE")) {
+    int a = 0, b = 0, cc = 0;
+    if (std::sscanf(e, "%d,%d,%d", &a, &b, &cc) == 3 && a > 0 && b > 0 && cc > 0) {
+      tile[0] = a; tile[1] = b; tile[2] = cc;
+    }
+  }
+  for (int k = 0; k < 3; ++k) c->tile[k] = tile[k];
+  std::vector<int64_t> key(g.V);
+  for (int lex = 0; lex < g.V; ++lex) {
+    int x[4], r = lex;
+    for (int mu = 0; mu < 4; ++mu) { x[mu] = r % L[mu]; r /= L[mu]; }
+    const int zc = (x[2] * 8) / L[2];
+    int64_t k = zc;
+    k = k * L[2] + x[2] / tile[2];
+    k = k * L[1] + x[1] / tile[1];
+    k = k * L[0] + x[0] / tile[0];
+    k = k * L[3] + x[3];
+    k = k * L[2] + x[2] % tile[2];
+    k = k * L[1] + x[1] % tile[1];
+    k = k * L[0] + x[0] % tile[0];
+    key[lex] = k;
+  }
+  c->h_site_lex.assign((size_t)2 * g.Vh, 0);
+  c->h_idx.assign((size_t)g.V, 0);
+  {
+    std::vector<int> order(g.V);
+    for (int i = 0; i < g.V; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+    int cnt[2] = {0, 0};
+    for (int lex : order) {
+      int x[4], r = lex;
+      for (int mu = 0; mu < 4; ++mu) { x[mu] = r % L[mu]; r /= L[mu]; }
+      const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+      const int i = cnt[p]++;
+      c->h_site_lex[(size_t)p * g.Vh + i] = lex;
+      c->h_idx[lex] = i;
+    }
+  }
+  // neighbour and boundary tables in the internal order
+  c->h_nbr.assign((size_t)2 * 8 * g.Vh, 0);
+  c->h_sign.assign((size_t)2 * 8 * g.Vh, 0);
+  for (int lex = 0; lex < g.V; ++lex) {
+    int x[4], r = lex;
+    for (int mu = 0; mu < 4; ++mu) { x[mu] = r % L[mu]; r /= L[mu]; }
+    const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+    const int i = c->h_idx[lex];
+    for (int d = 0; d < 8; ++d) {
+      const int mu = d & 3;
+      int y[4] = {x[0], x[1], x[2], x[3]};
+      int sg = 1;
+      if (d < 4) {
+        if (++y[mu] == L[mu]) { y[mu] = 0; sg = act->bc[mu]; }
+      } else {
+        if (--y[mu] < 0) { y[mu] = L[mu] - 1; sg = act->bc[mu]; }
+      }
+      const int yl = ((y[3] * L[2] + y[2]) * L[1] + y[1]) * L[0] + y[0];
+      c->h_nbr[((size_t)p * 8 + d) * g.Vh + i] = c->h_idx[yl];
+      c->h_sign[((size_t)p * 8 + d) * g.Vh + i] = (int8_t)sg;
+    }
+  }
+  c->h_mat = build_local_matrices(*act);
+  std::vector<float> m32(c->h_mat.begin(), c->h_mat.end());
+
+  size_t link_reals = (size_t)2 * 4 * g.Vh * 18;
+  hipError_t e = hipSuccess;
+  e = hipMalloc(&c->d_nbr, sizeof(int32_t) * c->h_nbr.size());
+  if (e == hipSuccess) e = hipMalloc(&c->d_site_lex, sizeof(int32_t) * c->h_site_lex.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(c->d_site_lex, c->h_site_lex.data(), sizeof(int32_t) * c->h_site_lex.size(),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&c->d_mat64, sizeof(double) * c->h_mat.size());
+  if (e == hipSuccess) e = hipMalloc(&c->d_mat32, sizeof(float) * m32.size());
+  for (int p = 0; p < 4 && e == hipSuccess; ++p) e = hipMalloc(&c->d_links[p], link_reals * prec_bytes(p));
+  if (e == hipSuccess)
+    e = hipMemcpy(c->d_nbr, c->h_nbr.data(), sizeof(int32_t) * c->h_nbr.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->d_mat64, c->h_mat.data(), sizeof(double) * c->h_mat.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->d_mat32, m32.data(), sizeof(float) * m32.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    const int code = (e == hipErrorOutOfMemory) ? QDWF_ENOMEM : QDWF_EDEVICE;
+    qdwf_destroy(c);
+    return fail(code, "device allocation in qdwf_create failed: %s", hipGetErrorString(e));
+  }
+  *out = c;
+  return QDWF_OK;
+}
+
+int qdwf_destroy(qdwf_ctx* ctx) {
+  if (!ctx) return QDWF_OK;
+  DeviceGuard dg(ctx->device);
+  if (ctx->d_nbr) (void)hipFree(ctx->d_nbr);
+  if (ctx->d_site_lex) (void)hipFree(ctx->d_site_lex);
+  if (ctx->d_mat64) (void)hipFree(ctx->d_mat64);
+  if (ctx->d_mat32) (void)hipFree(ctx->d_mat32);
+  for (int p = 0; p < 4; ++p)
+    if (ctx->d_links[p]) (void)hipFree(ctx->d_links[p]);
+  delete ctx;
+  return QDWF_OK;
+}
+
+int qdwf_set_gauge(qdwf_ctx* ctx, const void* U, int canon_prec, void* stream) {
+  CTX_CHECK(ctx);
+  TRY(check_ptr(U, "U"));
+  if (canon_prec != QDWF_F64 && canon_prec != QDWF_F32)
+    return fail(QDWF_EINVAL, "canon_prec must be QDWF_F64 or QDWF_F32");
+  DeviceGuard dg(ctx->device);
+  TRY(launch_pack_links(ctx, U, canon_prec, S(stream)));
+  ctx->gauge_set = true;
+  return QDWF_OK;
+}
+
+size_t qdwf_field_reals(const qdwf_ctx* ctx, int subset) {
+  if (!ctx) return 0;
+  return (size_t)(subset == QDWF_FULL ? 2 : 1) * ctx->g.n5h * 24;
+}
+
+static int check_subset(int subset) {
+  if (subset != QDWF_EVEN && subset != QDWF_ODD && subset != QDWF_FULL)
+    return fail(QDWF_EINVAL, "unknown subset %d", subset);
+  return QDWF_OK;
+}
+
+int qdwf_pack_spinor(qdwf_ctx* ctx, void* dst, int prec, int layout, const void* src,
+                     int src_prec, int subset, int nrhs, void* stream) {
+  CTX_CHECK(ctx);
+  TRY(check_ptr(dst, "dst"));
+  TRY(check_ptr(src, "src"));
+  TRY(check_prec(prec));
+  TRY(check_layout(layout));
+  TRY(check_subset(subset));
+  TRY(check_nrhs(nrhs));
+  DeviceGuard dg(ctx->device);
+  return launch_pack(ctx, dst, prec, layout, src, src_prec, subset, nrhs, S(stream), false);
+}
+
+int qdwf_unpack_spinor(qdwf_ctx* ctx, void* dst, int dst_prec, const void* src, int prec,
+                       int layout, int subset, int nrhs, void* stream) {
+  CTX_CHECK(ctx);
+  TRY(check_ptr(dst, "dst"));
+  TRY(check_ptr(src, "src"));
+  TRY(check_prec(prec));
+  TRY(check_layout(layout));
+  TRY(check_subset(subset));
+  TRY(check_nrhs(nrhs));
+  DeviceGuard dg(ctx->device);
+  return launch_pack(ctx, dst, prec, layout, src, dst_prec, subset, nrhs, S(stream), true);
+}
+
+static int common_checks(qdwf_ctx* ctx, const void* out, const void* in, int prec, int layout,
+                         int nrhs) {
+  CTX_CHECK(ctx);
+  TRY(check_ptr(out, "out"));
+  TRY(check_ptr(in, "in"));
+  TRY(check_prec(prec));
+  TRY(check_layout(layout));
+  TRY(check_nrhs(nrhs));
+  TRY(check_gauge(ctx));
+  return QDWF_OK;
+}
+
+static double alpha_of(const qdwf_ctx* c) { return c->act.b * (4.0 - c->act.M5) + 1.0; }
+static double beta_of(const qdwf_ctx* c) { return c->act.c * (4.0 - c->act.M5) - 1.0; }
+
+int qdwf_apply_D(qdwf_ctx* ctx, void* out, const void* in, int dagger, int prec, int layout,
+                 int nrhs, void* stream) {
+  TRY(common_checks(ctx, out, in, prec, layout, nrhs));
+  if (out == in) return fail(QDWF_EINVAL, "out must not alias in");
+  DeviceGuard dg(ctx->device);
+  const size_t bytes = prec_bytes(prec);
+  const long half = ctx->g.n5h * 24;
+  const char* ib = reinterpret_cast<const char*>(in);
+  char* ob = reinterpret_cast<char*>(out);
+  HopArgs a = {};
+  a.in[0] = ib + half * bytes;   // output even reads odd input
+  a.in[1] = ib;
+  a.out[0] = ob;
+  a.out[1] = ob + half * bytes;
+  a.z[0] = ib;
+  a.z[1] = ib + half * bytes;
+  a.rs_in = a.rs_out = a.rs_z = 2 * half;
+  a.par0 = 0;
+  a.npar = 2;
+  a.nrhs = nrhs;
+  a.epi = 1;
+  a.hop_scale = -0.5;
+  a.alpha = alpha_of(ctx);
+  a.beta = beta_of(ctx);
+  return launch_hop(ctx, prec, layout, dagger ? 1 : 0, a, S(stream));
+}
+
+int qdwf_apply_Mee(qdwf_ctx* ctx, void* out, const void* in, int subset, int dagger, int which,
+                   int prec, int layout, int nrhs, void* stream) {
+  CTX_CHECK(ctx);
+  TRY(check_ptr(out, "out"));
+  TRY(check_ptr(in, "in"));
+  TRY(check_prec(prec));
+  TRY(check_layout(layout));
+  TRY(check_nrhs(nrhs));
+  TRY(check_subset(subset));
+  if (which != QDWF_MEE_FWD && which != QDWF_MEE_INV) return fail(QDWF_EINVAL, "unknown operator %d", which);
+  DeviceGuard dg(ctx->device);
+  const long half = ctx->g.n5h * 24;
+  const int nh = subset == QDWF_FULL ? 2 : 1;
+  MatKind k = which == QDWF_MEE_FWD ? (dagger ? MAT_MEE_DAG : MAT_MEE)
+                                    : (dagger ? MAT_MEEINV_DAG : MAT_MEEINV);
+  return launch_local(ctx, prec, layout, k, out, in, nh, half, half * nh, nrhs, S(stream));
+}
+
+int qdwf_apply_Deo(qdwf_ctx* ctx, void* out, const void* in, int out_parity, int dagger,
+                   int prec, int layout, int nrhs, void* stream) {
+  TRY(common_checks(ctx, out, in, prec, layout, nrhs));
+  if (out_parity != QDWF_EVEN && out_parity != QDWF_ODD) return fail(QDWF_EINVAL, "out_parity must be 0 or 1");
+  if (out == in) return fail(QDWF_EINVAL, "out must not alias in");
+  DeviceGuard dg(ctx->device);
+  return apply_hop_parity(ctx, prec, layout, dagger ? 1 : 0, out_parity, out, in, nullptr, -0.5,
+                          nrhs, ctx->g.n5h * 24, S(stream));
+}
+
+size_t qdwf_workspace_bytes(const qdwf_ctx* ctx, int op, int prec, int nrhs) {
+  if (!ctx || nrhs < 1 || prec < QDWF_F64 || prec > QDWF_BF16) return 0;
+  const size_t half = (size_t)ctx->g.n5h * 24 * prec_bytes(prec) * nrhs;
+  const size_t al = (half + 255) & ~(size_t)255;
+  switch (op) {
+    case QDWF_OP_MPC: return 2 * al;
+    case QDWF_OP_MDAGM: return 3 * al;
+    case QDWF_OP_SOLVE: return solve_ws_bytes(ctx, prec, nrhs, 0);
+    case QDWF_OP_REDUCE: return dot_ws_bytes((long)ctx->g.n5h * 24 * 2, nrhs);
+  }
+  return 0;
+}
+
+int qdwf_apply_Mpc(qdwf_ctx* ctx, void* out, const void* in, int dagger, int prec, int layout,
+                   int nrhs, void* ws, void* stream) {
+  TRY(common_checks(ctx, out, in, prec, layout, nrhs));
+  TRY(check_ptr(ws, "ws"));
+  if (out == in) return fail(QDWF_EINVAL, "out must not alias in");
+  DeviceGuard dg(ctx->device);
+  const size_t half = (size_t)ctx->g.n5h * 24 * prec_bytes(prec) * nrhs;
+  const size_t al = (half + 255) & ~(size_t)255;
+  char* w = reinterpret_cast<char*>(ws);
+  return apply_mpc(ctx, prec, layout, dagger ? 1 : 0, out, in, w, w + al, nrhs,
+                   ctx->g.n5h * 24, S(stream));
+}
+
+int qdwf_apply_MdagM(qdwf_ctx* ctx, void* out, const void* in, int prec, int layout, int nrhs,
+                     void* ws, void* stream) {
+  TRY(common_checks(ctx, out, in, prec, layout, nrhs));
+  TRY(check_ptr(ws, "ws"));
+  if (out == in) return fail(QDWF_EINVAL, "out must not alias in");
+  DeviceGuard dg(ctx->device);
+  const size_t half = (size_t)ctx->g.n5h * 24 * prec_bytes(prec) * nrhs;
+  const size_t al = (half + 255) & ~(size_t)255;
+  char* w = reinterpret_cast<char*>(ws);
+  return apply_mdagm(ctx, prec, layout, out, in, w, w + al, w + 2 * al, nrhs, ctx->g.n5h * 24,
+                     S(stream));
+}
+
+int qdwf_dot(qdwf_ctx* ctx, double* out, const void* x, const void* y, int subset, int prec,
+             int layout, int nrhs, void* ws, void* stream) {
+  CTX_CHECK(ctx);
+  TRY(check_ptr(out, "out"));
+  TRY(check_ptr(x, "x"));
+  TRY(check_ptr(y, "y"));
+  TRY(check_ptr(ws, "ws"));
+  TRY(check_prec(prec));
+  TRY(check_layout(layout));
+  TRY(check_subset(subset));
+  TRY(check_nrhs(nrhs));
+  DeviceGuard dg(ctx->device);
+  const long n = (long)(subset == QDWF_FULL ? 2 : 1) * ctx->g.n5h * 24;
+  return dot_re_im(ctx, out, x, y, n, prec, layout, nrhs, ws, S(stream));
+}
+
+int qdwf_solve(qdwf_ctx* ctx, void* x, const void* b, int nrhs, const qdwf_solve_params* params,
+               qdwf_solve_stats* stats, void* ws, void* stream) {
+  CTX_CHECK(ctx);
+  TRY(check_ptr(x, "x"));
+  TRY(check_ptr(b, "b"));
+  TRY(check_ptr(params, "params"));
+  TRY(check_ptr(ws, "ws"));
+  TRY(check_nrhs(nrhs));
+  TRY(check_gauge(ctx));
+  qdwf_solve_params p = *params;
+  TRY(check_prec(p.inner_prec));
+  TRY(check_layout(p.layout));
+  if (p.system != QDWF_SYS_NORMAL_PC && p.system != QDWF_SYS_FULL)
+    return fail(QDWF_EINVAL, "unknown system %d", p.system);
+  if (!(p.tol > 0.0) || !(p.tol < 1.0)) return fail(QDWF_EINVAL, "tol must be in (0, 1)");
+  if (p.delta < 0.0 || p.delta >= 1.0) return fail(QDWF_EINVAL, "delta must be in [0, 1)");
+  if (p.check_every < 0 || p.check_every > 4096) return fail(QDWF_EINVAL, "check_every out of range");
+  if (x == b) return fail(QDWF_EINVAL, "x must not alias b");
+  DeviceGuard dg(ctx->device);
+  qdwf_solve_stats local = {};
+  qdwf_solve_stats* sp = stats ? stats : &local;
+  std::memset(sp, 0, sizeof(*sp));
+  const auto t0 = std::chrono::steady_clock::now();
+  // graphs cannot be captured on the null stream: run such a call on a
+  // private stream (the call is synchronous either way)
+  hipStream_t run = S(stream);
+  hipStream_t own = nullptr;
+  if (p.use_graph && run == nullptr) {
+    if (hipStreamSynchronize(nullptr) != hipSuccess ||
+        hipStreamCreateWithFlags(&own, hipStreamNonBlocking) != hipSuccess)
+      return fail(QDWF_EDEVICE, "could not create a stream for graph capture");
+    run = own;
+  }
+  const int rc = solve(ctx, reinterpret_cast<double*>(x), reinterpret_cast<const double*>(b), nrhs,
+                       p, sp, ws, run);
+  (void)hipStreamSynchronize(run);
+  if (own) (void)hipStreamDestroy(own);
+  sp->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (rc == QDWF_ENOTCONV) set_error("solver reached max_iter = %d before tol", p.max_iter);
+  if (rc == QDWF_ENAN) set_error("solver met NaN/Inf or a breakdown (p^dag A p <= 0)");
+  return rc;
+}
+
+int qdwf_geometry_tables(qdwf_ctx* ctx, int32_t* cb_of_lex, int32_t* nbr, int8_t* sign) {
+  CTX_CHECK(ctx);
+  const Geom& g = ctx->g;
+  if (cb_of_lex)
+    for (int l = 0; l < g.V; ++l) cb_of_lex[l] = ctx->h_idx[l];
+  // the kernels read [p][d][cb]; the exported order is [p][cb][d]
+  if (nbr) {
+    std::vector<int32_t> dev((size_t)2 * 8 * g.Vh);
+    DeviceGuard dg(ctx->device);
+    if (hipMemcpy(dev.data(), ctx->d_nbr, sizeof(int32_t) * dev.size(), hipMemcpyDeviceToHost) != hipSuccess)
+      return fail(QDWF_EDEVICE, "copy of the neighbour table failed");
+    for (int p = 0; p < 2; ++p)
+      for (int cb = 0; cb < g.Vh; ++cb)
+        for (int d = 0; d < 8; ++d) nbr[((size_t)p * g.Vh + cb) * 8 + d] = dev[((size_t)p * 8 + d) * g.Vh + cb];
+  }
+  if (sign)
+    for (int p = 0; p < 2; ++p)
+      for (int cb = 0; cb < g.Vh; ++cb)
+        for (int d = 0; d < 8; ++d)
+          sign[((size_t)p * g.Vh + cb) * 8 + d] = ctx->h_sign[((size_t)p * 8 + d) * g.Vh + cb];
+  return QDWF_OK;
+}
+
+}  // extern "C"

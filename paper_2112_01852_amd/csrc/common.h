@@ -1,0 +1,180 @@
+// Internal declarations of libqdwf: storage types, the context, launch helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "qdwf.h"
+
+namespace qdwf {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+int fail(int code, const char* fmt, ...);
+
+#define QDWF_HIP(call)                                                               \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return ::qdwf::fail(QDWF_EDEVICE, "%s failed: %s (%s:%d)", #call,             \
+                          hipGetErrorString(e_), __FILE__, __LINE__);                \
+  } while (0)
+
+// ---------------------------------------------------------- storage types
+// bf16 is kept as raw bits; conversions round to nearest even.
+struct bf16 {
+  uint16_t u;
+};
+
+template <class S> struct Store;
+
+// from64() converts an FP64 value with a single rounding (used by the packers).
+template <> struct Store<double> {
+  typedef double compute;
+  __device__ __host__ static inline double to(double v) { return v; }
+  __device__ __host__ static inline double from(double v) { return v; }
+  __device__ static inline double from64(double v) { return v; }
+};
+template <> struct Store<float> {
+  typedef float compute;
+  __device__ __host__ static inline float to(float v) { return v; }
+  __device__ __host__ static inline float from(float v) { return v; }
+  __device__ static inline float from64(double v) { return (float)v; }
+};
+// FP32 value of v rounded to odd: correct final rounding to any format with
+// at least two fewer significand bits (round-to-odd, Boldo and Melquiond).
+__device__ inline float round_to_odd_f32(double v) {
+  float f = (float)v;
+  if ((double)f != v) {
+    uint32_t u = __float_as_uint(f);
+    if (!(u & 1u)) u = (fabs((double)f) < fabs(v)) ? u + 1u : u - 1u;
+    f = __uint_as_float(u);
+  }
+  return f;
+}
+template <> struct Store<_Float16> {
+  typedef float compute;
+  __device__ static inline float to(_Float16 v) { return (float)v; }
+  __device__ static inline _Float16 from(float v) { return (_Float16)v; }
+  __device__ static inline _Float16 from64(double v) { return (_Float16)round_to_odd_f32(v); }
+};
+template <> struct Store<bf16> {
+  typedef float compute;
+  __device__ static inline float to(bf16 v) { return __uint_as_float(((uint32_t)v.u) << 16); }
+  __device__ static inline bf16 from(float v) {
+    uint32_t x = __float_as_uint(v);
+    bf16 r;
+    if ((x & 0x7f800000u) == 0x7f800000u && (x & 0x007fffffu)) {
+      r.u = (uint16_t)((x >> 16) | 0x40);  // quiet NaN
+    } else {
+      x += 0x7fffu + ((x >> 16) & 1u);
+      r.u = (uint16_t)(x >> 16);
+    }
+    return r;
+  }
+  __device__ static inline bf16 from64(double v) { return from(round_to_odd_f32(v)); }
+};
+
+inline size_t prec_bytes(int prec) {
+  switch (prec) {
+    case QDWF_F64: return 8;
+    case QDWF_F32: return 4;
+    default: return 2;
+  }
+}
+
+// Calls f.template operator()<S>() with S the storage type of `prec`.
+template <class F>
+int dispatch_prec(int prec, F&& f) {
+  switch (prec) {
+    case QDWF_F64: return f.template operator()<double>();
+    case QDWF_F32: return f.template operator()<float>();
+    case QDWF_F16: return f.template operator()<_Float16>();
+    case QDWF_BF16: return f.template operator()<bf16>();
+  }
+  return fail(QDWF_EINVAL, "unknown precision %d", prec);
+}
+
+// -------------------------------------------------------------- geometry
+struct Geom {
+  int L[4];
+  int Ls;
+  int V;      // 4D volume
+  int Vh;     // V/2
+  long n5h;   // Vh*Ls: 5D sites of one parity
+};
+
+// 5D-local chiral matrices (Ls x Ls per chirality) kept on device.
+enum MatKind { MAT_MEE = 0, MAT_MEE_DAG, MAT_MEEINV, MAT_MEEINV_DAG, MAT_COUNT };
+
+// Launch shape of the hop kernel, chosen per (precision, layout, nrhs) by
+// the tuner or by the default rule.
+struct HopShape {
+  int threads;   // threads per block (multiple of 64)
+  int nrb;       // right-hand sides per block
+  int xcd;       // 1: XCD-aware block order
+  int lds_pad;   // extra LDS bytes per block: caps the blocks resident per CU
+};
+
+}  // namespace qdwf
+
+struct qdwf_ctx {
+  qdwf_action act;
+  int device;
+  qdwf::Geom g;
+  int32_t* d_nbr;          // [2][8][Vh] neighbour internal index
+  int32_t* d_site_lex;     // [2][Vh] lex index of each internal site
+  int tile[3];             // (x, y, z) tile of the traversal order
+  void* d_links[4];        // per precision: [2][4][Vh][18] reals, bc folded in
+  bool gauge_set;
+  double* d_mat64;         // [MAT_COUNT][2][Ls][Ls]
+  float* d_mat32;
+  std::vector<double> h_mat;  // host copy
+  std::vector<int32_t> h_nbr; // host copy [2][8][Vh]
+  std::vector<int32_t> h_site_lex;  // [2][Vh]
+  std::vector<int32_t> h_idx;       // [V] internal index of each lex site
+  std::vector<int8_t> h_sign; // [2][8][Vh]
+};
+
+namespace qdwf {
+
+// ------------------------------------------------------ kernel launchers
+// Hop family. One launch computes, for every output parity p in
+// [par0, par0 + npar) and every right-hand side r,
+//   h      = D_h   chi          (dagger = 0, chi = A in)  or
+//   h      = A^dag D_h^dag in   (dagger = 1)
+//   out    = hop_scale * h + [epi] (alpha z + beta C z)   (C^dag when dagger)
+// in[p] is the half field of parity 1-p feeding output parity p; z[p] is at
+// parity p. rhs strides are in reals.
+struct HopArgs {
+  const void* in[2];
+  void* out[2];
+  const void* z[2];
+  long rs_in, rs_out, rs_z;
+  int par0, npar;
+  int nrhs;
+  int epi;
+  double hop_scale, alpha, beta;
+};
+int launch_hop(qdwf_ctx* ctx, int prec, int layout, int dagger, const HopArgs& a,
+               hipStream_t st, const HopShape* shape = nullptr);
+
+// out = K in with K the chiral Ls x Ls matrices of `kind`, on `nhalf` half
+// fields of nrhs right-hand sides each (half fields are consecutive with
+// stride rs_half reals inside one rhs block of stride rs reals).
+int launch_local(qdwf_ctx* ctx, int prec, int layout, MatKind kind, void* out, const void* in,
+                 int nhalf, long rs_half, long rs, int nrhs, hipStream_t st);
+
+int launch_pack(qdwf_ctx* ctx, void* dst, int prec, int layout, const void* src, int src_prec,
+                int subset, int nrhs, hipStream_t st, bool unpack);
+int launch_pack_links(qdwf_ctx* ctx, const void* U, int canon_prec, hipStream_t st);
+
+// Default hop launch shape and tuner cache lookup.
+HopShape default_shape(const qdwf_ctx* ctx, int prec, int nrhs);
+bool tuned_shape(const qdwf_ctx* ctx, int prec, int layout, int dagger, int nrhs, HopShape* out);
+
+}  // namespace qdwf

@@ -1,0 +1,627 @@
+// The Domain Wall kernel: the 4D Wilson hop D_h applied on every slice of the
+// fifth dimension (the paper's "performance-relevant part of the Domain Wall
+// operator", Section 4.1; 1320 flops per 5D site in Table 3), fused with the
+// Mobius 5D factors and the 4D-local epilogue so that one pass over memory
+// gives D, D^dag, M_pq, (M_qp)^dag, or the last stage of M_pc / M_pc^dag.
+//
+// Work decomposition (one lane per 5D site and right-hand side):
+//   * a wavefront holds floor(64/Ls) groups of Ls lanes; the lanes of a group
+//     are the Ls slices of one (4D site, rhs) pair, so the s +- 1 neighbours
+//     needed by the 5D operator C live in the same wavefront and are fetched
+//     with cross-lane permutes instead of memory reloads;
+//   * a block covers nsb consecutive checkerboard sites times nrb right-hand
+//     sides; the 8 links of each of its 4D sites (4 forward U_mu(x), 4 backward
+//     U_mu(x-mu)) are staged once in LDS and shared by all Ls*nrb lanes of the
+//     site (Section 4.2 credits the Domain Wall kernel's advantage over Wilson
+//     Dslash to exactly this reuse of links across the fifth dimension);
+//   * the spin projection (1 -+ g_mu) reduces each neighbour spinor to a
+//     half spinor before the SU(3) multiply, so only 2 colour vectors are
+//     multiplied per direction (Table 3 counts this as 1320 flops per site);
+//   * blocks are renumbered so that each XCD (its own L2) walks a contiguous
+//     range of the lattice.
+#include <cstdlib>
+
+#include "common.h"
+
+namespace qdwf {
+
+namespace {
+
+struct HopK {
+  const void* in[2];
+  void* out[2];
+  const void* z[2];
+  const void* links;   // [2][4][Vh][18] in the storage type
+  const int* nbr;      // [2][8][Vh]
+  long rs_in, rs_out, rs_z, plane;
+  int Vh, Ls, nrhs, par0, npar;
+  int nsb, nrb, gpw, nrblk;
+  int epi, xcd;
+  double c_over_b, mf, hop_scale_b, alpha, beta;
+};
+
+__device__ inline int xcd_remap(int bid, int nb) {
+  // hardware hands block i to XCD i % 8; give XCD x a contiguous range instead
+  const int per = nb >> 3, rem = nb & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return (x < rem) ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
+}
+
+// ------------------------------------------------------------ site I/O
+// Register order of the 24 reals of a site: v[(spin*3 + colour)*2 + re/im].
+template <class S, int LAYOUT> struct SiteIO;
+
+template <class S> struct SiteIO<S, QDWF_RRII> {
+  typedef typename Store<S>::compute T;
+  __device__ static inline void load(const S* __restrict__ f, long j, long plane, T* v) {
+#pragma unroll
+    for (int sc = 0; sc < 12; ++sc) {
+      v[2 * sc] = Store<S>::to(f[(long)sc * plane + j]);
+      v[2 * sc + 1] = Store<S>::to(f[(long)(12 + sc) * plane + j]);
+    }
+  }
+  __device__ static inline void store(S* __restrict__ f, long j, long plane, const T* v) {
+#pragma unroll
+    for (int sc = 0; sc < 12; ++sc) {
+      f[(long)sc * plane + j] = Store<S>::from(v[2 * sc]);
+      f[(long)(12 + sc) * plane + j] = Store<S>::from(v[2 * sc + 1]);
+    }
+  }
+};
+
+template <> struct SiteIO<double, QDWF_RIRI> {
+  __device__ static inline void load(const double* __restrict__ f, long j, long, double* v) {
+    const double2* p = reinterpret_cast<const double2*>(f + j * 24);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+      const double2 q = p[k];
+      v[2 * k] = q.x;
+      v[2 * k + 1] = q.y;
+    }
+  }
+  __device__ static inline void store(double* __restrict__ f, long j, long, const double* v) {
+    double2* p = reinterpret_cast<double2*>(f + j * 24);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) p[k] = make_double2(v[2 * k], v[2 * k + 1]);
+  }
+};
+
+template <> struct SiteIO<float, QDWF_RIRI> {
+  __device__ static inline void load(const float* __restrict__ f, long j, long, float* v) {
+    const float4* p = reinterpret_cast<const float4*>(f + j * 24);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const float4 q = p[k];
+      v[4 * k] = q.x;
+      v[4 * k + 1] = q.y;
+      v[4 * k + 2] = q.z;
+      v[4 * k + 3] = q.w;
+    }
+  }
+  __device__ static inline void store(float* __restrict__ f, long j, long, const float* v) {
+    float4* p = reinterpret_cast<float4*>(f + j * 24);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) p[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
+  }
+};
+
+// 16-bit storage: 24 reals = 48 bytes = 3 x 16-byte loads.
+template <class S> struct SiteIO16 {
+  __device__ static inline void load(const S* __restrict__ f, long j, long, float* v) {
+    const uint4* p = reinterpret_cast<const uint4*>(f + j * 24);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const uint4 q = p[k];
+      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        v[8 * k + 2 * m] = Store<S>::to(bits<S>((uint16_t)(w[m] & 0xffffu)));
+        v[8 * k + 2 * m + 1] = Store<S>::to(bits<S>((uint16_t)(w[m] >> 16)));
+      }
+    }
+  }
+  __device__ static inline void store(S* __restrict__ f, long j, long, const float* v) {
+    uint4* p = reinterpret_cast<uint4*>(f + j * 24);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      uint32_t w[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+        w[m] = (uint32_t)raw(Store<S>::from(v[8 * k + 2 * m])) |
+               ((uint32_t)raw(Store<S>::from(v[8 * k + 2 * m + 1])) << 16);
+      p[k] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
+  template <class X> __device__ static inline X bits(uint16_t u);
+  __device__ static inline uint16_t raw(_Float16 h) { return __builtin_bit_cast(uint16_t, h); }
+  __device__ static inline uint16_t raw(bf16 h) { return h.u; }
+};
+template <> template <> __device__ inline _Float16 SiteIO16<_Float16>::bits<_Float16>(uint16_t u) {
+  return __builtin_bit_cast(_Float16, u);
+}
+template <> template <> __device__ inline bf16 SiteIO16<bf16>::bits<bf16>(uint16_t u) {
+  bf16 r;
+  r.u = u;
+  return r;
+}
+template <> struct SiteIO<_Float16, QDWF_RIRI> : SiteIO16<_Float16> {};
+template <> struct SiteIO<bf16, QDWF_RIRI> : SiteIO16<bf16> {};
+
+// ----------------------------------------------- spin projection algebra
+// The constants below are compile-time, and every case is written out so that
+// no multiply by 0 or +-1 and no add of 0 reaches the instruction stream (IEEE
+// rules forbid the compiler from dropping those itself).
+template <class T> __device__ inline T fmac(T a, T b, T c);
+template <> __device__ inline float fmac<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ inline double fmac<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// o = a + c b with c in {+1, -1, +i, -i} given as (CR, CI)
+template <int CR, int CI, class T>
+__device__ inline void cadd(const T* a, const T* b, T* o) {
+  if constexpr (CR == 1) { o[0] = a[0] + b[0]; o[1] = a[1] + b[1]; }
+  else if constexpr (CR == -1) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; }
+  else if constexpr (CI == 1) { o[0] = a[0] - b[1]; o[1] = a[1] + b[0]; }
+  else { o[0] = a[0] + b[1]; o[1] = a[1] - b[0]; }
+}
+// o = c b
+template <int CR, int CI, class T>
+__device__ inline void cset(const T* b, T* o) {
+  if constexpr (CR == 1) { o[0] = b[0]; o[1] = b[1]; }
+  else if constexpr (CR == -1) { o[0] = -b[0]; o[1] = -b[1]; }
+  else if constexpr (CI == 1) { o[0] = -b[1]; o[1] = b[0]; }
+  else { o[0] = b[1]; o[1] = -b[0]; }
+}
+
+// Half spinor h = first two rows of (1 + SG g_MU) v, h[(hs*3 + colour)*2 + re/im].
+template <int MU, int SG, class T>
+__device__ inline void project(const T* v, T* h) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T* s0 = v + (0 * 3 + a) * 2;
+    const T* s1 = v + (1 * 3 + a) * 2;
+    const T* s2 = v + (2 * 3 + a) * 2;
+    const T* s3 = v + (3 * 3 + a) * 2;
+    T* h0 = h + (0 * 3 + a) * 2;
+    T* h1 = h + (1 * 3 + a) * 2;
+    if constexpr (MU == 0) {        // h0 = s0 + SG i s3 ; h1 = s1 + SG i s2
+      cadd<0, SG>(s0, s3, h0);
+      cadd<0, SG>(s1, s2, h1);
+    } else if constexpr (MU == 1) { // h0 = s0 - SG s3 ; h1 = s1 + SG s2
+      cadd<-SG, 0>(s0, s3, h0);
+      cadd<SG, 0>(s1, s2, h1);
+    } else if constexpr (MU == 2) { // h0 = s0 + SG i s2 ; h1 = s1 - SG i s3
+      cadd<0, SG>(s0, s2, h0);
+      cadd<0, -SG>(s1, s3, h1);
+    } else {                        // h0 = s0 + SG s2 ; h1 = s1 + SG s3
+      cadd<SG, 0>(s0, s2, h0);
+      cadd<SG, 0>(s1, s3, h1);
+    }
+  }
+}
+
+// acc (+)= (1 + SG g_MU) psi rebuilt from the multiplied half spinor u:
+// rows 0,1 are u0,u1; rows 2,3 are fixed multiples of u0 or u1.
+template <int MU, int SG, bool FIRST, class T>
+__device__ inline void recon_acc(const T* u, T* acc) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T* u0 = u + (0 * 3 + a) * 2;
+    const T* u1 = u + (1 * 3 + a) * 2;
+    T* r0 = acc + (0 * 3 + a) * 2;
+    T* r1 = acc + (1 * 3 + a) * 2;
+    T* r2 = acc + (2 * 3 + a) * 2;
+    T* r3 = acc + (3 * 3 + a) * 2;
+    // r2 = c2 u_j2, r3 = c3 u_j3 with (c, j) from the gamma matrix
+    constexpr int C2R = MU == 1 ? SG : (MU == 3 ? SG : 0);
+    constexpr int C2I = MU == 0 ? -SG : (MU == 2 ? -SG : 0);
+    constexpr int C3R = MU == 1 ? -SG : (MU == 3 ? SG : 0);
+    constexpr int C3I = MU == 0 ? -SG : (MU == 2 ? SG : 0);
+    const T* j2 = (MU == 0 || MU == 1) ? u1 : u0;
+    const T* j3 = (MU == 0 || MU == 1) ? u0 : u1;
+    if constexpr (FIRST) {
+      r0[0] = u0[0]; r0[1] = u0[1];
+      r1[0] = u1[0]; r1[1] = u1[1];
+      cset<C2R, C2I>(j2, r2);
+      cset<C3R, C3I>(j3, r3);
+    } else {
+      r0[0] += u0[0]; r0[1] += u0[1];
+      r1[0] += u1[0]; r1[1] += u1[1];
+      cadd<C2R, C2I>(r2, j2, r2);
+      cadd<C3R, C3I>(r3, j3, r3);
+    }
+  }
+}
+
+// u[hs][a] = sum_b M[a][b] h[hs][b] with M = U (DAGL = false) or U^dag:
+// one multiply and five fused multiply-adds per real output.
+template <bool DAGL, class T>
+__device__ inline void su3_mul(const T* U, const T* h, T* u) {
+#pragma unroll
+  for (int hs = 0; hs < 2; ++hs)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T* hh = h + hs * 6;
+      T re, im;
+      if constexpr (!DAGL) {
+        const T* m = U + a * 6;   // row a: U[a][b] at m + 2b
+        re = m[0] * hh[0];
+        im = m[0] * hh[1];
+        re = fmac(-m[1], hh[1], re);
+        im = fmac(m[1], hh[0], im);
+#pragma unroll
+        for (int b = 1; b < 3; ++b) {
+          re = fmac(m[2 * b], hh[2 * b], re);
+          im = fmac(m[2 * b], hh[2 * b + 1], im);
+          re = fmac(-m[2 * b + 1], hh[2 * b + 1], re);
+          im = fmac(m[2 * b + 1], hh[2 * b], im);
+        }
+      } else {
+        // conj(U[b][a]) at column a of row b: U + b*6 + 2a
+        const T* m = U + 2 * a;
+        re = m[0] * hh[0];
+        im = m[0] * hh[1];
+        re = fmac(m[1], hh[1], re);
+        im = fmac(-m[1], hh[0], im);
+#pragma unroll
+        for (int b = 1; b < 3; ++b) {
+          const T* mb = m + 6 * b;
+          re = fmac(mb[0], hh[2 * b], re);
+          im = fmac(mb[0], hh[2 * b + 1], im);
+          re = fmac(mb[1], hh[2 * b + 1], re);
+          im = fmac(-mb[1], hh[2 * b], im);
+        }
+      }
+      u[(hs * 3 + a) * 2] = re;
+      u[(hs * 3 + a) * 2 + 1] = im;
+    }
+}
+
+// Link staging stride in LDS (reals per link): 16-byte aligned rows.
+template <class T> struct LinkStride { static constexpr int v = 20; };
+template <> struct LinkStride<double> { static constexpr int v = 18; };
+
+template <class T>
+__device__ inline void load_link(const T* __restrict__ p, T* U) {
+  if constexpr (sizeof(T) == 4) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float4 w = q[k];
+      U[4 * k] = w.x; U[4 * k + 1] = w.y; U[4 * k + 2] = w.z; U[4 * k + 3] = w.w;
+    }
+    const float2 w = *reinterpret_cast<const float2*>(p + 16);
+    U[16] = w.x; U[17] = w.y;
+  } else {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double2 w = q[k];
+      U[2 * k] = w.x; U[2 * k + 1] = w.y;
+    }
+  }
+}
+
+// A link (3x3 complex, 18 reals) from global memory: 8-byte loads for the
+// 32- and 64-bit types (a link starts on an 8-byte boundary), 4-byte loads for
+// the 16-bit types.
+template <class S> struct LinkIO {
+  typedef typename Store<S>::compute T;
+  __device__ static inline void load(const S* __restrict__ p, T* U) {
+    if constexpr (sizeof(S) == 8) {
+      const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const double2 w = q[k];
+        U[2 * k] = (T)w.x; U[2 * k + 1] = (T)w.y;
+      }
+    } else if constexpr (sizeof(S) == 4) {
+      const float2* q = reinterpret_cast<const float2*>(p);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const float2 w = q[k];
+        U[2 * k] = (T)w.x; U[2 * k + 1] = (T)w.y;
+      }
+    } else {
+      const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const uint32_t w = q[k];
+        S a, b;
+        __builtin_memcpy(&a, &w, 2);
+        const uint32_t hi = w >> 16;
+        __builtin_memcpy(&b, &hi, 2);
+        U[2 * k] = Store<S>::to(a); U[2 * k + 1] = Store<S>::to(b);
+      }
+    }
+  }
+};
+
+template <int N> struct IC { static constexpr int value = N; };
+
+// Values of the lanes holding slices s-1 and s+1 of the same (site, rhs)
+// group. With Ls = 16 a group is one 16-lane DPP row and the exchange is a
+// row rotate (no LDS round trip); otherwise a cross-lane permute.
+__device__ inline int dpp_ror1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x121, 0xF, 0xF, false); }
+__device__ inline int dpp_ror15(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x12F, 0xF, 0xF, false); }
+template <bool DPP16> struct SShift {
+  int src_m, src_p;
+  template <class T> __device__ inline T m(T v) const { return __shfl(v, src_m, 64); }
+  template <class T> __device__ inline T p(T v) const { return __shfl(v, src_p, 64); }
+};
+template <> struct SShift<true> {
+  int src_m, src_p;
+  __device__ inline float m(float v) const { return __int_as_float(dpp_ror1(__float_as_int(v))); }
+  __device__ inline float p(float v) const { return __int_as_float(dpp_ror15(__float_as_int(v))); }
+  __device__ inline double m(double v) const {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_ror1((int)b), hi = dpp_ror1((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+  __device__ inline double p(double v) const {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_ror15((int)b), hi = dpp_ror15((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  }
+};
+
+// Target occupancy (waves per SIMD) the register allocator plans for: two for
+// 32- and 64-bit storage, whose arithmetic needs the registers to keep two
+// directions' neighbour loads in flight, three for 16-bit storage.
+template <class S> struct WavesPerEU { static constexpr int v = sizeof(S) >= 4 ? 2 : 3; };
+
+template <class S, int LAYOUT, bool DAG, bool DPP16>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_kernel(HopK k) {
+  typedef typename Store<S>::compute T;
+  constexpr int LSTR = LinkStride<T>::v;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* su = reinterpret_cast<T*>(smem);                       // [nsb][8][LSTR]
+  int* snb = reinterpret_cast<int*>(su + (size_t)8 * LSTR * k.nsb);   // [8][nsb]
+
+  // logical block: right-hand-side block fastest, then parity, then sites;
+  // the XCD remap hands each XCD a contiguous range of logical blocks
+  const int L = k.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int rb = L % k.nrblk;
+  const int t1 = L / k.nrblk;
+  const int p = k.par0 + t1 % k.npar;
+  const int sb = t1 / k.npar;
+  const int q = 1 - p;
+  const int cb0 = sb * k.nsb;
+  const int Vh = k.Vh;
+
+  // Stage the neighbour indices of the block's sites (one load per thread),
+  // then start this lane's first two neighbour-spinor loads, then stage the
+  // links with every load of this thread in flight at once, so the block pays
+  // about two memory latencies before its arithmetic starts.
+  const int* nbp = k.nbr + (long)p * 8 * Vh;
+  for (int i = threadIdx.x; i < 8 * k.nsb; i += blockDim.x) {
+    const int d = i / k.nsb, sl = i - d * k.nsb;
+    const int cb = min(cb0 + sl, Vh - 1);
+    snb[i] = nbp[(long)d * Vh + cb];
+  }
+  __syncthreads();
+
+  const int Ls = k.Ls;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gl = lane / Ls, s = lane - gl * Ls;
+  const bool lane_ok = gl < k.gpw;
+  const int gid = wave * k.gpw + (lane_ok ? gl : 0);
+  const int sl = gid / k.nrb, rl = gid - sl * k.nrb;
+  const int cb = cb0 + sl, r = rb * k.nrb + rl;
+  const bool active = lane_ok && cb < Vh && r < k.nrhs;
+  const int rc = min(r, k.nrhs - 1);
+  const int cbc = min(cb, Vh - 1);
+  const S* in = reinterpret_cast<const S*>(k.in[p]) + (long)rc * k.rs_in;
+  const int* nbs = snb + sl;
+
+  T va[24], vb[24];   // two neighbour spinors in flight
+  SiteIO<S, LAYOUT>::load(in, (long)nbs[0] * Ls + s, k.plane, va);
+  SiteIO<S, LAYOUT>::load(in, (long)nbs[k.nsb] * Ls + s, k.plane, vb);
+
+  {
+    // one thread per link: 18 contiguous reals, loaded with vector loads
+    const S* lk = reinterpret_cast<const S*>(k.links);
+    const int nlink = 8 * k.nsb;
+    for (int i = threadIdx.x; i < nlink; i += blockDim.x) {
+      const int d = i / k.nsb, sl2 = i - d * k.nsb;
+      const int mu = d & 3;
+      int par, site;
+      if (d < 4) { par = p; site = min(cb0 + sl2, Vh - 1); }
+      else       { par = q; site = snb[d * k.nsb + sl2]; }
+      T Ul[18];
+      LinkIO<S>::load(lk + (((long)par * 4 + mu) * Vh + site) * 18, Ul);
+      T* dstp = su + (sl2 * 8 + d) * LSTR;
+#pragma unroll
+      for (int c = 0; c < 18; ++c) dstp[c] = Ul[c];
+    }
+  }
+  __syncthreads();
+
+  const int base = gl * Ls;
+  SShift<DPP16> sh;
+  sh.src_m = lane_ok ? base + (s == 0 ? Ls - 1 : s - 1) : lane;   // holds slice s-1
+  sh.src_p = lane_ok ? base + (s == Ls - 1 ? 0 : s + 1) : lane;   // holds slice s+1
+  const T mf = (T)k.mf;
+  const T wm = (s == 0) ? -mf : (T)1;        // wall factor of S_d at this slice
+  const T wp = (s == Ls - 1) ? -mf : (T)1;   // wall factor of S_u at this slice
+  // A = b (1 + (c/b) C); the factor b is applied once at the end
+  const T cb_ = (T)k.c_over_b;
+  const T cm = cb_ * wm, cp = cb_ * wp;
+  const T* lks = su + sl * 8 * LSTR;
+
+  T acc[24];
+  // direction D uses the buffer loaded two steps earlier and refills it with
+  // direction D + 2
+  auto step = [&](auto Dc) {
+    constexpr int D = decltype(Dc)::value;
+    constexpr int MU = D & 3;
+    constexpr bool FWD = D < 4;
+    // (1 - g) on forward hops and (1 + g) on backward ones; swapped for D_h^dag
+    constexpr int SG = (FWD != DAG) ? -1 : +1;
+    T* buf = (D & 1) ? vb : va;
+    T v[24];
+#pragma unroll
+    for (int i = 0; i < 24; ++i) v[i] = buf[i];
+    if constexpr (D < 6)
+      SiteIO<S, LAYOUT>::load(in, (long)nbs[(D + 2) * k.nsb] * Ls + s, k.plane, buf);
+    if constexpr (!DAG) {
+      // chi / b = psi + (c/b) (P+ psi_{s-1} + P- psi_{s+1}), walls included
+#pragma unroll
+      for (int i = 0; i < 12; ++i) v[i] = fmac(cm, sh.m(v[i]), v[i]);
+#pragma unroll
+      for (int i = 12; i < 24; ++i) v[i] = fmac(cp, sh.p(v[i]), v[i]);
+    }
+    T h[12], uh[12], U[18];
+    load_link(lks + D * LSTR, U);
+    project<MU, SG>(v, h);
+    su3_mul<!FWD>(U, h, uh);
+    recon_acc<MU, SG, D == 0>(uh, acc);
+  };
+  step(IC<0>()); step(IC<1>()); step(IC<2>()); step(IC<3>());
+  step(IC<4>()); step(IC<5>()); step(IC<6>()); step(IC<7>());
+
+  if constexpr (DAG) {
+    // A^dag h / b = h + (c/b) C^dag h, C^dag = P- S_d + P+ S_u:
+    // upper spins come from s+1, lower spins from s-1
+    T tmp[24];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) tmp[i] = fmac(cp, sh.p(acc[i]), acc[i]);
+#pragma unroll
+    for (int i = 12; i < 24; ++i) tmp[i] = fmac(cm, sh.m(acc[i]), acc[i]);
+#pragma unroll
+    for (int i = 0; i < 24; ++i) acc[i] = tmp[i];
+  }
+  const T hs = (T)k.hop_scale_b;   // hop scale times b
+  const long j = (long)cbc * Ls + s;
+  if (k.epi) {
+    const S* zf = reinterpret_cast<const S*>(k.z[p]) + (long)rc * k.rs_z;
+    T z[24];
+    SiteIO<S, LAYOUT>::load(zf, j, k.plane, z);
+    const T al = (T)k.alpha, be = (T)k.beta;
+    const T bm = be * wm, bp = be * wp;
+#pragma unroll
+    for (int i = 0; i < 24; ++i) acc[i] = fmac(al, z[i], hs * acc[i]);
+    if constexpr (!DAG) {  // + beta C z
+#pragma unroll
+      for (int i = 0; i < 12; ++i) acc[i] = fmac(bm, sh.m(z[i]), acc[i]);
+#pragma unroll
+      for (int i = 12; i < 24; ++i) acc[i] = fmac(bp, sh.p(z[i]), acc[i]);
+    } else {               // + beta C^dag z
+#pragma unroll
+      for (int i = 0; i < 12; ++i) acc[i] = fmac(bp, sh.p(z[i]), acc[i]);
+#pragma unroll
+      for (int i = 12; i < 24; ++i) acc[i] = fmac(bm, sh.m(z[i]), acc[i]);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 24; ++i) acc[i] *= hs;
+  }
+  if (active) {
+    S* out = reinterpret_cast<S*>(k.out[p]) + (long)rc * k.rs_out;
+    SiteIO<S, LAYOUT>::store(out, j, k.plane, acc);
+  }
+}
+
+template <class S, int LAYOUT, bool DAG, bool DPP16>
+int run_hop_k(qdwf_ctx* ctx, int prec, const HopArgs& a, hipStream_t st, const HopShape& sh) {
+  typedef typename Store<S>::compute T;
+  const Geom& g = ctx->g;
+  HopK k;
+  for (int i = 0; i < 2; ++i) { k.in[i] = a.in[i]; k.out[i] = a.out[i]; k.z[i] = a.z[i]; }
+  k.links = ctx->d_links[prec];
+  k.nbr = ctx->d_nbr;
+  k.rs_in = a.rs_in; k.rs_out = a.rs_out; k.rs_z = a.rs_z;
+  k.plane = g.n5h;
+  k.Vh = g.Vh; k.Ls = g.Ls; k.nrhs = a.nrhs; k.par0 = a.par0; k.npar = a.npar;
+  k.gpw = 64 / g.Ls;
+  const int G = (sh.threads / 64) * k.gpw;
+  k.nrb = sh.nrb;
+  k.nsb = G / sh.nrb;
+  k.nrblk = (a.nrhs + k.nrb - 1) / k.nrb;
+  const int nsblk = (g.Vh + k.nsb - 1) / k.nsb;
+  k.epi = a.epi; k.xcd = sh.xcd;
+  k.c_over_b = ctx->act.c / ctx->act.b;
+  k.mf = ctx->act.mf;
+  k.hop_scale_b = a.hop_scale * ctx->act.b;
+  k.alpha = a.alpha; k.beta = a.beta;
+  const size_t lds = (size_t)8 * LinkStride<T>::v * k.nsb * sizeof(T) + (size_t)8 * k.nsb * sizeof(int) +
+                    (size_t)sh.lds_pad;
+  if (lds > 64 * 1024) return fail(QDWF_EINVAL, "hop launch shape needs %zu bytes of LDS", lds);
+  dim3 grid(nsblk * k.nrblk * a.npar), block(sh.threads);
+  hipLaunchKernelGGL((hop_kernel<S, LAYOUT, DAG, DPP16>), grid, block, lds, st, k);
+  QDWF_HIP(hipGetLastError());
+  return QDWF_OK;
+}
+
+template <class S, int LAYOUT, bool DAG>
+int run_hop(qdwf_ctx* ctx, int prec, const HopArgs& a, hipStream_t st, const HopShape& sh) {
+  if (ctx->g.Ls == 16) return run_hop_k<S, LAYOUT, DAG, true>(ctx, prec, a, st, sh);
+  return run_hop_k<S, LAYOUT, DAG, false>(ctx, prec, a, st, sh);
+}
+
+}  // namespace
+
+HopShape default_shape(const qdwf_ctx* ctx, int prec, int nrhs) {
+  HopShape sh;
+  // at most 32 (site, rhs) groups per block: bounds the LDS link stage
+  // (32 sites x 8 links x 18 reals, 36 KB in FP64) for every Ls
+  const int gpw = 64 / ctx->g.Ls;
+  int waves = 32 / gpw;
+  if (waves < 1) waves = 1;
+  if (waves > 4) waves = 4;
+  sh.threads = 64 * waves;
+  sh.xcd = 1;
+  const int G = waves * gpw;
+  int nrb = 1;
+  for (int d = 1; d <= G; ++d)
+    if (G % d == 0 && d <= nrhs) nrb = d;
+  // keep at least 4 sites per block so the link staging amortises
+  while (nrb > 1 && G / nrb < 4) {
+    int nd = nrb - 1;
+    while (nd > 1 && G % nd) --nd;
+    nrb = nd;
+  }
+  sh.nrb = nrb;
+  sh.lds_pad = 0;
+  if (const char* e = std::getenv("QDWF_HOP_LDS_PAD")) sh.lds_pad = std::atoi(e);
+  if (const char* e = std::getenv("QDWF_HOP_THREADS")) {
+    const int t = std::atoi(e);
+    if (t >= 64 && t <= 256 && t % 64 == 0) {
+      sh.threads = t;
+      const int G2 = (t / 64) * gpw;
+      sh.nrb = 1;
+      for (int d = 1; d <= G2; ++d)
+        if (G2 % d == 0 && d <= nrhs && G2 / d >= 4) sh.nrb = d;
+    }
+  }
+  (void)prec;
+  return sh;
+}
+
+int launch_hop(qdwf_ctx* ctx, int prec, int layout, int dagger, const HopArgs& a,
+               hipStream_t st, const HopShape* shape) {
+  HopShape sh;
+  if (shape) sh = *shape;
+  else if (!tuned_shape(ctx, prec, layout, dagger, a.nrhs, &sh)) sh = default_shape(ctx, prec, a.nrhs);
+  const int G = (sh.threads / 64) * (64 / ctx->g.Ls);
+  if (sh.threads % 64 || sh.threads < 64 || sh.threads > 256 || sh.nrb < 1 || G % sh.nrb)
+    return fail(QDWF_EINVAL, "invalid hop launch shape (threads %d, nrb %d)", sh.threads, sh.nrb);
+  auto go = [&](auto tag_s) -> int {
+    typedef decltype(tag_s) S;
+    if (layout == QDWF_RIRI) {
+      return dagger ? run_hop<S, QDWF_RIRI, true>(ctx, prec, a, st, sh)
+                    : run_hop<S, QDWF_RIRI, false>(ctx, prec, a, st, sh);
+    }
+    return dagger ? run_hop<S, QDWF_RRII, true>(ctx, prec, a, st, sh)
+                  : run_hop<S, QDWF_RRII, false>(ctx, prec, a, st, sh);
+  };
+  switch (prec) {
+    case QDWF_F64: return go(double());
+    case QDWF_F32: return go(float());
+    case QDWF_F16: return go(_Float16());
+    case QDWF_BF16: return go(bf16());
+  }
+  return fail(QDWF_EINVAL, "unknown precision %d", prec);
+}
+
+}  // namespace qdwf

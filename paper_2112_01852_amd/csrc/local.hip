@@ -1,0 +1,177 @@
+// 4D-local operators of the even-odd scheme: M_ee = alpha + beta C, its
+// inverse, and their adjoints. At each 4D site they act on the Ls slices of
+// one chirality at a time with a real Ls x Ls matrix (C = P- S_u + P+ S_d, so
+// the upper spins 0,1 see S_d and the lower spins 2,3 see S_u). The matrices
+// are built once per action on the host:
+//   M_ee       upper alpha + beta S_d,  lower alpha + beta S_u
+//   M_ee^dag   the transposes
+//   M_ee^-1    (1/alpha) sum_k rho^k S^k / (1 + mf rho^Ls), rho = -beta/alpha,
+//              with S = S_d (upper) or S_u (lower); the adjoint is its transpose.
+// Kernel: the Ls lanes of a (site, rhs) group stage their 24 reals in LDS, then
+// each lane forms its output slice as an Ls-term sum over the staged column.
+#include <cmath>
+
+#include "common.h"
+
+namespace qdwf {
+
+namespace {
+
+template <class S, int LAYOUT>
+__device__ inline void ld(const S* f, long j, long plane, typename Store<S>::compute* v) {
+  if (LAYOUT == QDWF_RIRI) {
+#pragma unroll
+    for (int c = 0; c < 24; ++c) v[c] = Store<S>::to(f[j * 24 + c]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 24; ++c) v[c] = Store<S>::to(f[(long)((c & 1) * 12 + (c >> 1)) * plane + j]);
+  }
+}
+
+template <class S, int LAYOUT>
+__device__ inline void st(S* f, long j, long plane, const typename Store<S>::compute* v) {
+  if (LAYOUT == QDWF_RIRI) {
+#pragma unroll
+    for (int c = 0; c < 24; ++c) f[j * 24 + c] = Store<S>::from(v[c]);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 24; ++c) f[(long)((c & 1) * 12 + (c >> 1)) * plane + j] = Store<S>::from(v[c]);
+  }
+}
+
+// grid: x = site blocks, y = half index * nrhs + rhs
+template <class S, int LAYOUT>
+__global__ void __launch_bounds__(256) local_kernel(const S* in, S* out,
+                                                    const typename Store<S>::compute* __restrict__ K,
+                                                    int Vh, int Ls, long plane, long rs_half,
+                                                    long rs, int nhalf) {
+  typedef typename Store<S>::compute T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* col = reinterpret_cast<T*>(smem);           // [groups][Ls][24]
+  T* km = col + (blockDim.x / 64) * (64 / Ls) * Ls * 24;   // [2][Ls][Ls]
+  for (int i = threadIdx.x; i < 2 * Ls * Ls; i += blockDim.x) km[i] = K[i];
+
+  const int gpw = 64 / Ls;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gl = lane / Ls, s = lane - gl * Ls;
+  const bool lane_ok = gl < gpw;
+  const int gid = wave * gpw + (lane_ok ? gl : 0);
+  const int G = (blockDim.x / 64) * gpw;
+  const int cb = blockIdx.x * G + gid;
+  const bool active = lane_ok && cb < Vh;
+  const int cbc = min(cb, Vh - 1);
+  const int h = blockIdx.y % nhalf, r = blockIdx.y / nhalf;
+  const long off = (long)r * rs + (long)h * rs_half;
+  const long j = (long)cbc * Ls + s;
+
+  T v[24];
+  ld<S, LAYOUT>(in + off, j, plane, v);
+  if (lane_ok) {
+#pragma unroll
+    for (int c = 0; c < 24; ++c) col[(gid * Ls + s) * 24 + c] = v[c];
+  }
+  __syncthreads();
+  if (!active) return;
+  T o[24];
+#pragma unroll
+  for (int c = 0; c < 24; ++c) o[c] = 0;
+  const T* ku = km + s * Ls;              // upper chirality row s
+  const T* kl = km + Ls * Ls + s * Ls;    // lower chirality row s
+  const T* cg = col + gid * Ls * 24;
+  for (int t = 0; t < Ls; ++t) {
+    const T a = ku[t], b = kl[t];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) o[c] += a * cg[t * 24 + c];
+#pragma unroll
+    for (int c = 12; c < 24; ++c) o[c] += b * cg[t * 24 + c];
+  }
+  st<S, LAYOUT>(out + off, j, plane, o);
+}
+
+}  // namespace
+
+// Host construction of the chiral matrices of every kind: [kind][2][Ls][Ls].
+std::vector<double> build_local_matrices(const qdwf_action& a) {
+  const int Ls = a.Ls;
+  const double al = a.b * (4.0 - a.M5) + 1.0;
+  const double be = a.c * (4.0 - a.M5) - 1.0;
+  std::vector<double> Su(Ls * Ls, 0.0), Sd(Ls * Ls, 0.0);
+  for (int s = 0; s < Ls; ++s) {
+    if (s + 1 < Ls) Su[s * Ls + s + 1] = 1.0; else Su[s * Ls] = -a.mf;
+    if (s > 0) Sd[s * Ls + s - 1] = 1.0; else Sd[s * Ls + Ls - 1] = -a.mf;
+  }
+  std::vector<double> out((size_t)MAT_COUNT * 2 * Ls * Ls, 0.0);
+  auto at = [&](int kind, int chir, int s, int t) -> double& {
+    return out[(((size_t)kind * 2 + chir) * Ls + s) * Ls + t];
+  };
+  const double rho = -be / al;
+  const double den = al * (1.0 + a.mf * std::pow(rho, Ls));
+  for (int chir = 0; chir < 2; ++chir) {
+    const std::vector<double>& S = chir == 0 ? Sd : Su;
+    // powers of S accumulate the inverse series
+    std::vector<double> P(Ls * Ls, 0.0), Q(Ls * Ls, 0.0);
+    for (int s = 0; s < Ls; ++s) P[s * Ls + s] = 1.0;
+    double rk = 1.0;
+    std::vector<double> inv(Ls * Ls, 0.0);
+    for (int k = 0; k < Ls; ++k) {
+      for (int i = 0; i < Ls * Ls; ++i) inv[i] += rk * P[i] / den;
+      // P <- P S
+      for (int s = 0; s < Ls; ++s)
+        for (int t = 0; t < Ls; ++t) {
+          double acc = 0;
+          for (int m = 0; m < Ls; ++m) acc += P[s * Ls + m] * S[m * Ls + t];
+          Q[s * Ls + t] = acc;
+        }
+      P.swap(Q);
+      rk *= rho;
+    }
+    for (int s = 0; s < Ls; ++s)
+      for (int t = 0; t < Ls; ++t) {
+        const double m = (s == t ? al : 0.0) + be * S[s * Ls + t];
+        at(MAT_MEE, chir, s, t) = m;
+        at(MAT_MEE_DAG, chir, t, s) = m;
+        at(MAT_MEEINV, chir, s, t) = inv[s * Ls + t];
+        at(MAT_MEEINV_DAG, chir, t, s) = inv[s * Ls + t];
+      }
+  }
+  return out;
+}
+
+int launch_local(qdwf_ctx* ctx, int prec, int layout, MatKind kind, void* out, const void* in,
+                 int nhalf, long rs_half, long rs, int nrhs, hipStream_t st) {
+  const Geom& g = ctx->g;
+  auto go = [&](auto stag) -> int {
+    typedef decltype(stag) S;
+    typedef typename Store<S>::compute T;
+    // largest block (<= 256 threads) whose staged columns fit in 48 KB of LDS
+    int threads = 256;
+    while (threads > 64 &&
+           ((size_t)(threads / 64) * (64 / g.Ls) * g.Ls * 24 + 2 * g.Ls * g.Ls) * sizeof(T) > 48 * 1024)
+      threads /= 2;
+    const int G = (threads / 64) * (64 / g.Ls);
+    dim3 grid((g.Vh + G - 1) / G, nhalf * nrhs), block(threads);
+    const T* K;
+    if (sizeof(T) == 8) K = reinterpret_cast<const T*>(ctx->d_mat64 + (size_t)kind * 2 * g.Ls * g.Ls);
+    else K = reinterpret_cast<const T*>(ctx->d_mat32 + (size_t)kind * 2 * g.Ls * g.Ls);
+    const size_t lds = ((size_t)G * g.Ls * 24 + 2 * g.Ls * g.Ls) * sizeof(T);
+    if (layout == QDWF_RIRI)
+      hipLaunchKernelGGL((local_kernel<S, QDWF_RIRI>), grid, block, lds, st,
+                         reinterpret_cast<const S*>(in), reinterpret_cast<S*>(out), K, g.Vh, g.Ls,
+                         g.n5h, rs_half, rs, nhalf);
+    else
+      hipLaunchKernelGGL((local_kernel<S, QDWF_RRII>), grid, block, lds, st,
+                         reinterpret_cast<const S*>(in), reinterpret_cast<S*>(out), K, g.Vh, g.Ls,
+                         g.n5h, rs_half, rs, nhalf);
+    QDWF_HIP(hipGetLastError());
+    return QDWF_OK;
+  };
+  switch (prec) {
+    case QDWF_F64: return go(double());
+    case QDWF_F32: return go(float());
+    case QDWF_F16: return go(_Float16());
+    case QDWF_BF16: return go(bf16());
+  }
+  return fail(QDWF_EINVAL, "unknown precision %d", prec);
+}
+
+}  // namespace qdwf

@@ -1,0 +1,123 @@
+"""CG solves on the GPU against the oracle's CG and the FP64 true residual.
+
+Every solve must reach an FP64 true residual <= 1e-10 and agree with the
+oracle's solution (solved to 1e-13) to 1e-8 relative; the lattices and links
+used here have condition numbers of a few hundred, so 1e-10 in the residual
+bounds the solution error well below 1e-8.
+"""
+import numpy as np
+import pytest
+
+from oracle import cpu
+from paper_2112_01852_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+MOBIUS = dict(M5=1.8, mf=0.01, b=1.5, c=0.5)
+
+
+def _rel(x, y):
+    return float(np.linalg.norm((x - y).ravel()) / np.linalg.norm(y.ravel()))
+
+
+@pytest.fixture(scope="module")
+def q():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_01852_amd import qdwf
+    qdwf.lib()
+    return qdwf
+
+
+@pytest.fixture(scope="module")
+def setup(q):
+    L, Ls = (4, 4, 4, 6), 8
+    a = cpu.Action(L=L, Ls=Ls, **MOBIUS)
+    U = I.gauge_field(L, "smooth", 3000, eps=0.3)
+    b = cpu.restrict(I.gaussian_spinor(L, Ls, 3001), L, 1)
+    x_ref, it, res = cpu.cg(a, U, b, tol=1e-13)
+    assert res < 1e-12
+    D = q.Dirac(L, Ls, **MOBIUS)
+    D.set_gauge(U)
+    yield q, a, U, b, x_ref, D
+    D.close()
+
+
+def _solve(q, D, b, inner, layout=1, nrhs=1, **kw):
+    bf = D.pack(b, q.QDWF_F64, layout, q.QDWF_ODD, nrhs)
+    x = D.field(q.QDWF_F64, q.QDWF_ODD, nrhs)
+    ws = D.workspace(q.QDWF_OP_SOLVE, inner, nrhs)
+    prm = q.solve_params(inner_prec=inner, layout=layout, tol=1e-10, **kw)
+    rc, st = q.qdwf_solve(D.ctx, x, bf, nrhs, prm, ws)
+    return rc, st, D.unpack(x, q.QDWF_F64, layout, q.QDWF_ODD, nrhs).cpu().numpy()
+
+
+@pytest.mark.parametrize("inner", [0, 1, 2, 3])
+@pytest.mark.parametrize("layout", [0, 1])
+def test_solve_normal_pc(setup, inner, layout):
+    q, a, U, b, x_ref, D = setup
+    rc, st, x = _solve(q, D, b, inner, layout)
+    assert rc == q.QDWF_OK, q.qdwf_last_error()
+    assert st.true_residual <= 1e-10
+    # independent FP64 residual with the oracle operator
+    r = b - cpu.mpc(a, U, cpu.mpc(a, U, x), dagger=True)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.5e-10
+    assert _rel(x, x_ref) <= 1e-8
+    if inner != 0:
+        assert st.reliable_updates >= 1
+
+
+def test_multi_rhs_solve_matches_single(setup):
+    q, a, U, b, x_ref, D = setup
+    nrhs = 3
+    bs = np.stack([b, 2.0 * cpu.restrict(I.gaussian_spinor(a.L, a.Ls, 9), a.L, 1), 0.5 * b])
+    rc, st, xs = _solve(q, D, bs, 1, nrhs=nrhs)
+    assert rc == q.QDWF_OK and st.converged == nrhs
+    for j in range(nrhs):
+        rc1, st1, x1 = _solve(q, D, bs[j], 1)
+        assert np.array_equal(xs[j], x1), f"rhs {j} differs between batched and alone"
+
+
+def test_graph_replay_matches_eager(setup):
+    q, a, U, b, x_ref, D = setup
+    rc0, st0, x0 = _solve(q, D, b, 1, use_graph=0, check_every=5)
+    rc1, st1, x1 = _solve(q, D, b, 1, use_graph=1, check_every=5)
+    assert rc0 == rc1 == q.QDWF_OK
+    assert st0.iterations == st1.iterations
+    assert np.array_equal(x0, x1)
+    # a second solve reuses nothing stale
+    rc2, st2, x2 = _solve(q, D, b, 1, use_graph=1, check_every=5)
+    assert np.array_equal(x1, x2)
+
+
+def test_full_system_point_source(q):
+    L, Ls = (4, 4, 4, 4), 8
+    a = cpu.Action(L=L, Ls=Ls, **MOBIUS)
+    U = I.gauge_field(L, "smooth", 4000, eps=0.3)
+    src = I.point_source(L, Ls, 2, 1)
+    D = q.Dirac(L, Ls, **MOBIUS)
+    D.set_gauge(U)
+    for inner in (0, 1):
+        bf = D.pack(src, q.QDWF_F64, 1, q.QDWF_FULL)
+        x = D.field(q.QDWF_F64, q.QDWF_FULL)
+        ws = D.workspace(q.QDWF_OP_SOLVE, inner)
+        prm = q.solve_params(system=q.QDWF_SYS_FULL, inner_prec=inner, tol=1e-10)
+        rc, st = q.qdwf_solve(D.ctx, x, bf, 1, prm, ws)
+        assert rc == q.QDWF_OK, q.qdwf_last_error()
+        xs = D.unpack(x, q.QDWF_F64, 1, q.QDWF_FULL).cpu().numpy()
+        assert st.full_residual <= 1e-10
+        r = cpu.dwf(a, U, xs) - src
+        assert np.linalg.norm(r) / np.linalg.norm(src) <= 1.5e-10
+    D.close()
+
+
+def test_not_converged_and_nan_are_reported(setup):
+    q, a, U, b, x_ref, D = setup
+    rc, st, x = _solve(q, D, b, 0, max_iter=3, check_every=1)
+    assert rc == q.QDWF_ENOTCONV
+    assert st.iterations == 3 and st.true_residual > 1e-10
+    bad = b.copy()
+    bad[np.unravel_index(np.argmax(np.abs(b)), b.shape)] = np.nan
+    rc, st, x = _solve(q, D, bad, 1)
+    assert rc == q.QDWF_ENAN
