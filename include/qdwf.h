@@ -216,6 +216,44 @@ int qdwf_dot(qdwf_ctx* ctx, double* out, const void* x, const void* y, int subse
 int qdwf_solve(qdwf_ctx* ctx, void* x, const void* b, int nrhs, const qdwf_solve_params* params,
                qdwf_solve_stats* stats, void* ws, void* stream);
 
+/* ---- serving pool ----------------------------------------------------- */
+/* Continuous batching of independent solves of M_pc^dag M_pc x_o = b_o, each
+ * with its own lattice, action, gauge field and source. Requests wait in FIFO
+ * order until their device footprint (qdwf_request_bytes) fits the pool's
+ * HBM budget and one of max_slots slots is free; admitted requests each run
+ * on their slot's stream and advance by one round (check_every inner
+ * iterations, or a reliable update) per qdwf_pool_step, with every round of
+ * a step launched before any is waited for, so requests overlap on the
+ * device. A request's result does not depend on what else is in the pool.
+ * Admission and retirement allocate and free the request's device memory. */
+typedef struct qdwf_pool qdwf_pool;
+
+typedef struct {
+  qdwf_action act;            /* lattice and action of this solve                   */
+  const void* U;              /* canonical gauge field, complex128, device          */
+  const void* b;              /* canonical source, complex128, device; odd sites used */
+  void* x_out;                /* canonical complex128 device buffer; odd sites are  */
+                              /* written when the request finishes                   */
+  qdwf_solve_params params;   /* system is taken as QDWF_SYS_NORMAL_PC; x0 = 0      */
+} qdwf_request;               /* U, b, x_out must stay valid until the request ends */
+
+/* Device bytes a request occupies while admitted. */
+size_t qdwf_request_bytes(const qdwf_action* act, const qdwf_solve_params* params);
+int qdwf_pool_create(int device, size_t hbm_budget, int max_slots, qdwf_pool** out);
+int qdwf_pool_destroy(qdwf_pool* pool);
+/* Queues a request (never blocks); QDWF_EINVAL if it can never fit the budget. */
+int qdwf_pool_submit(qdwf_pool* pool, const qdwf_request* req, uint64_t* id);
+/* One scheduling step: advance every admitted request by one round, admit
+ * queued requests that fit, retire finished ones. *n_active (may be NULL)
+ * receives the number of requests still admitted. */
+int qdwf_pool_step(qdwf_pool* pool, int* n_active);
+/* QDWF_EBUSY while the request is queued or running; otherwise its solve
+ * status (QDWF_OK, QDWF_ENOTCONV, QDWF_ENAN, ...) with stats filled, after
+ * which the id is forgotten. */
+int qdwf_pool_poll(qdwf_pool* pool, uint64_t id, qdwf_solve_stats* stats);
+/* Bytes admitted now and at peak, and the numbers of admitted and queued requests. */
+int qdwf_pool_info(qdwf_pool* pool, size_t* in_use, size_t* peak, int* n_active, int* n_queued);
+
 /* ---- geometry (tests) ------------------------------------------------- */
 /* Copies the tables the kernels use into host buffers: cb_of_lex[V] (int32:
  * the internal index i of each lex site within its parity), nbr[2][V/2][8]

@@ -41,6 +41,12 @@ int fail(int code, const char* fmt, ...) {
 
 std::vector<double> build_local_matrices(const qdwf_action& a);
 
+size_t ctx_bytes(const qdwf_action& a) {
+  const size_t V = (size_t)a.L[0] * a.L[1] * a.L[2] * a.L[3], Vh = V / 2;
+  const size_t mats = (size_t)MAT_COUNT * 2 * a.Ls * a.Ls * (8 + 4);
+  return 2 * 8 * Vh * 4 + 2 * Vh * 4 + 2 * 4 * Vh * 18 * (8 + 4 + 2 + 2) + mats + 8 * 256;
+}
+
 }  // namespace qdwf
 
 using namespace qdwf;

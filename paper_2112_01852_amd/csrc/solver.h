@@ -38,4 +38,22 @@ size_t solve_ws_bytes(const qdwf_ctx* ctx, int inner, int nrhs, int system);
 int solve(qdwf_ctx* ctx, double* x, const double* b, int nrhs, const qdwf_solve_params& prm,
           qdwf_solve_stats* stats, void* ws, hipStream_t st);
 
+// Resumable normal-equation CG on odd half fields (stride = one half field):
+// begin() launches the set-up, then complete() waits for the last round and
+// launch() starts the next one, until complete() reports finished.
+struct Solver {
+  virtual ~Solver() {}
+  virtual int begin() = 0;
+  virtual int launch() = 0;
+  virtual int complete(bool* finished) = 0;
+  virtual void fill_stats(qdwf_solve_stats* stats) const = 0;
+  virtual int result() const = 0;
+};
+Solver* make_solver(qdwf_ctx* ctx, const qdwf_solve_params& prm, int nrhs, double* x,
+                    const double* b, void* ws, hipStream_t st);
+
+// Geometry-only sizes used for admission control.
+size_t ctx_bytes(const qdwf_action& a);
+size_t solve_ws_bytes_for(const qdwf_action& a, int inner, int nrhs);
+
 }  // namespace qdwf

@@ -292,6 +292,11 @@ __global__ void __launch_bounds__(RT) k_ru_apply(const double* __restrict__ rh,
   }
 }
 
+__global__ void k_force_update(RhsState* st, int nrhs) {
+  for (int q = threadIdx.x; q < nrhs; q += blockDim.x)
+    if (st[q].status == ST_RUN) st[q].status = ST_UPDATE;
+}
+
 __global__ void k_init_state(RhsState* st, const double* part, int NB, int nrhs) {
   // bb from the partials of |b|^2
   __shared__ double sh[RT];
@@ -452,7 +457,7 @@ Layout solver_layout(long n, int nrhs, int inner) {
 }
 
 template <class S, class R>
-struct Cg {
+struct Cg : Solver {
   qdwf_ctx* ctx;
   hipStream_t st;
   int layout, inner, nrhs;
@@ -513,107 +518,139 @@ struct Cg {
     return QDWF_OK;
   }
 
-  int fetch_state() {
-    QDWF_HIP(hipMemcpyAsync(h_state.data(), d_state, sizeof(RhsState) * nrhs,
-                            hipMemcpyDeviceToHost, st));
-    QDWF_HIP(hipStreamSynchronize(st));
+  // ---- resumable driver: begin(), then alternately complete() and launch()
+  qdwf_solve_params prm;
+  RhsState* h_pin = nullptr;     // pinned host copy of the device states
+  hipEvent_t ev = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int status = QDWF_OK;
+  bool final_round = false;
+
+  ~Cg() override {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ev) (void)hipEventDestroy(ev);
+    if (h_pin) (void)hipHostFree(h_pin);
+  }
+
+  int fetch_async() {
+    QDWF_HIP(hipMemcpyAsync(h_pin, d_state, sizeof(RhsState) * nrhs, hipMemcpyDeviceToHost, st));
+    QDWF_HIP(hipEventRecord(ev, st));
     return QDWF_OK;
   }
 
-  int run(const qdwf_solve_params& prm, qdwf_solve_stats* stats) {
+  int begin() override {
     int rc;
-    h_state.resize(nrhs);
     d_state = at<RhsState>(L.off_state);
     hop_applications = 0;
-    // |b|^2 and state init
+    QDWF_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_pin), sizeof(RhsState) * nrhs));
+    QDWF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     hipLaunchKernelGGL((k_dot<double, double>), grid(), dim3(RT), 0, st, b, b, n, rs_b, rs_b, part());
     hipLaunchKernelGGL(k_init_state, dim3(nrhs), dim3(RT), 0, st, d_state, part(), NB, nrhs);
     hipLaunchKernelGGL((k_zero<R>), grid(), dim3(RT), 0, st, at<R>(L.off_xl), n, n);
     if (!prm.x0_is_guess) hipLaunchKernelGGL((k_zero<double>), grid(), dim3(RT), 0, st, xh, n, rs_x);
     QDWF_HIP(hipGetLastError());
     if ((rc = reliable_update(true))) return rc;
-    if ((rc = fetch_state())) return rc;
+    return fetch_async();
+  }
 
+  // Waits for the last launched round and decides; *finished is set once the
+  // solve is over (status holds the outcome).
+  int complete(bool* finished) override {
+    QDWF_HIP(hipEventSynchronize(ev));
+    h_state.assign(h_pin, h_pin + nrhs);
+    bool any_run = false, any_upd = false, bad = false;
+    for (const RhsState& s : h_state) {
+      any_run |= s.status == ST_RUN;
+      any_upd |= s.status == ST_UPDATE;
+      bad |= s.status == ST_NAN || s.status == ST_BREAKDOWN;
+    }
+    *finished = false;
+    if (bad) { status = QDWF_ENAN; *finished = true; }
+    else if (final_round) {
+      bool all_done = true;
+      for (const RhsState& s : h_state) all_done &= s.status == ST_DONE;
+      status = all_done ? QDWF_OK : QDWF_ENOTCONV;
+      *finished = true;
+    } else if (!any_run && !any_upd) { status = QDWF_OK; *finished = true; }
+    return QDWF_OK;
+  }
+
+  // Launches the next round (asynchronously): a reliable update if one is
+  // due, otherwise `check_every` inner iterations; ends with a state fetch.
+  int launch() override {
+    int rc = 0;
+    bool any_upd = false;
+    int max_it = 0;
+    for (const RhsState& s : h_state) {
+      any_upd |= s.status == ST_UPDATE;
+      if (s.status == ST_RUN && s.iters > max_it) max_it = s.iters;
+    }
     const int k = prm.check_every > 0 ? prm.check_every : 8;
     const int max_iter = prm.max_iter > 0 ? prm.max_iter : 20000;
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    int status = QDWF_OK;
-    int done_iters = 0;
+    if (any_upd) {
+      if ((rc = reliable_update(false))) return rc;
+      return fetch_async();
+    }
+    if (max_it >= max_iter) {
+      // out of iterations: fold the pending increment into x and report the
+      // true residual of what the solve reached
+      hipLaunchKernelGGL(k_force_update, dim3(1), dim3(64), 0, st, d_state, nrhs);
+      if ((rc = reliable_update(false))) return rc;
+      final_round = true;
+      return fetch_async();
+    }
+    const int batch = std::min(k, max_iter - max_it);
+    if (prm.use_graph && batch == k) {
+      if (!gexec) {
+        QDWF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        const int64_t h0 = hop_applications;
+        for (int i = 0; i < k && !rc; ++i) rc = inner_iteration();
+        hop_applications = h0;
+        const hipError_t e = hipStreamEndCapture(st, &graph);
+        if (rc) return rc;
+        if (e != hipSuccess) return fail(QDWF_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        QDWF_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+      }
+      QDWF_HIP(hipGraphLaunch(gexec, st));
+      hop_applications += 4 * k;
+    } else {
+      rc = 0;
+      for (int i = 0; i < batch && !rc; ++i) rc = inner_iteration();
+      if (rc) return rc;
+    }
+    return fetch_async();
+  }
+
+  int result() const override { return status; }
+
+  void fill_stats(qdwf_solve_stats* stats) const override {
+    if (!stats) return;
+    stats->iterations = 0;
+    stats->reliable_updates = 0;
+    stats->converged = 0;
+    stats->true_residual = 0;
+    for (const RhsState& s : h_state) {
+      stats->iterations = std::max(stats->iterations, s.iters);
+      stats->reliable_updates = std::max(stats->reliable_updates, s.ru);
+      stats->converged += s.status == ST_DONE;
+      const double res = s.bb > 0 ? std::sqrt(s.rr_true / s.bb) : 0.0;
+      stats->true_residual = std::max(stats->true_residual, res);
+    }
+    stats->flops += hop_applications * (int64_t)1320 * ctx->g.n5h * nrhs;
+  }
+
+  int run(qdwf_solve_stats* stats) {
+    int rc = begin();
+    if (rc) return rc;
     for (;;) {
-      bool any_run = false, any_upd = false, any_nan = false, any_brk = false;
-      int max_it = 0;
-      for (const RhsState& s : h_state) {
-        any_run |= s.status == ST_RUN;
-        any_upd |= s.status == ST_UPDATE;
-        any_nan |= s.status == ST_NAN;
-        any_brk |= s.status == ST_BREAKDOWN;
-        if (s.iters > max_it) max_it = s.iters;
-      }
-      if (any_nan || any_brk) { status = QDWF_ENAN; break; }
-      if (any_upd || (!any_run)) {
-        if (!any_upd) break;   // everything converged
-        if ((rc = reliable_update(false))) { status = rc; break; }
-        if ((rc = fetch_state())) { status = rc; break; }
-        continue;
-      }
-      if (max_it >= max_iter) {
-        // fold the pending increment into x and report the true residual
-        for (int q = 0; q < nrhs; ++q)
-          if (h_state[q].status == ST_RUN) h_state[q].status = ST_UPDATE;
-        QDWF_HIP(hipMemcpyAsync(d_state, h_state.data(), sizeof(RhsState) * nrhs,
-                                hipMemcpyHostToDevice, st));
-        if ((rc = reliable_update(false))) { status = rc; break; }
-        if ((rc = fetch_state())) { status = rc; break; }
-        bool all_done = true;
-        for (const RhsState& s : h_state) all_done &= s.status == ST_DONE;
-        status = all_done ? QDWF_OK : QDWF_ENOTCONV;
-        break;
-      }
-      const int batch = std::min(k, max_iter - max_it);
-      if (prm.use_graph) {
-        if (!gexec) {
-          QDWF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-          int64_t h0 = hop_applications;
-          for (int i = 0; i < k; ++i)
-            if ((rc = inner_iteration())) break;
-          hop_applications = h0;
-          hipError_t e = hipStreamEndCapture(st, &graph);
-          if (rc) { status = rc; break; }
-          if (e != hipSuccess) { status = fail(QDWF_EDEVICE, "graph capture failed: %s", hipGetErrorString(e)); break; }
-          QDWF_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
-        }
-        if (batch == k) {
-          QDWF_HIP(hipGraphLaunch(gexec, st));
-          hop_applications += 4 * k;
-        } else {
-          for (int i = 0; i < batch && !rc; ++i) rc = inner_iteration();
-          if (rc) { status = rc; break; }
-        }
-      } else {
-        for (int i = 0; i < batch && !rc; ++i) rc = inner_iteration();
-        if (rc) { status = rc; break; }
-      }
-      done_iters += batch;
-      if ((rc = fetch_state())) { status = rc; break; }
+      bool fin = false;
+      if ((rc = complete(&fin))) return rc;
+      if (fin) break;
+      if ((rc = launch())) return rc;
     }
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (stats) {
-      stats->iterations = 0;
-      stats->reliable_updates = 0;
-      stats->converged = 0;
-      stats->true_residual = 0;
-      for (const RhsState& s : h_state) {
-        stats->iterations = std::max(stats->iterations, s.iters);
-        stats->reliable_updates = std::max(stats->reliable_updates, s.ru);
-        stats->converged += s.status == ST_DONE;
-        const double res = s.bb > 0 ? std::sqrt(s.rr_true / s.bb) : 0.0;
-        stats->true_residual = std::max(stats->true_residual, res);
-      }
-      stats->flops += hop_applications * (int64_t)1320 * ctx->g.n5h * nrhs;
-    }
-    (void)done_iters;
+    fill_stats(stats);
     return status;
   }
 };
@@ -638,6 +675,46 @@ int axpby64(double* out, const double* a, double ca, const double* b, double cb,
                      rs_o, rs_a, rs_b);
   QDWF_HIP(hipGetLastError());
   return QDWF_OK;
+}
+
+size_t solve_ws_bytes_for(const qdwf_action& a, int inner, int nrhs) {
+  const long n = (long)a.L[0] * a.L[1] * a.L[2] * a.L[3] / 2 * a.Ls * 24;
+  return solver_layout(n, nrhs, inner).total;
+}
+
+Solver* make_solver(qdwf_ctx* ctx, const qdwf_solve_params& prm, int nrhs, double* x,
+                    const double* b, void* ws, hipStream_t st) {
+  const long n = ctx->g.n5h * 24;
+  auto mk = [&](auto stag, auto rtag) -> Solver* {
+    typedef decltype(stag) S;
+    typedef decltype(rtag) R;
+    Cg<S, R>* cg = new Cg<S, R>();
+    cg->ctx = ctx;
+    cg->st = st;
+    cg->layout = prm.layout;
+    cg->inner = prm.inner_prec;
+    cg->nrhs = nrhs;
+    cg->n = n;
+    cg->NB = reduce_blocks(n);
+    cg->ws = reinterpret_cast<char*>(ws);
+    cg->L = solver_layout(n, nrhs, prm.inner_prec);
+    cg->xh = x;
+    cg->rs_x = n;
+    cg->b = b;
+    cg->rs_b = n;
+    const double delta = prm.delta > 0 ? prm.delta : 0.1;
+    cg->delta2 = prm.inner_prec == QDWF_F64 ? 0.0 : delta * delta;
+    cg->tol2 = prm.tol * prm.tol;
+    cg->prm = prm;
+    return cg;
+  };
+  switch (prm.inner_prec) {
+    case QDWF_F64: return mk(double(), double());
+    case QDWF_F32: return mk(float(), float());
+    case QDWF_F16: return mk(_Float16(), float());
+    case QDWF_BF16: return mk(bf16(), float());
+  }
+  return nullptr;
 }
 
 size_t solve_ws_bytes(const qdwf_ctx* ctx, int inner, int nrhs, int system) {
@@ -672,7 +749,8 @@ static int solve_normal(qdwf_ctx* ctx, double* x, const double* b, int nrhs,
     const double delta = prm.delta > 0 ? prm.delta : 0.1;
     cg.delta2 = prm.inner_prec == QDWF_F64 ? 0.0 : delta * delta;
     cg.tol2 = tol * tol;
-    return cg.run(prm, stats);
+    cg.prm = prm;
+    return cg.run(stats);
   };
   switch (prm.inner_prec) {
     case QDWF_F64: return go(double(), double());

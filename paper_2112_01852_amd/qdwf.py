@@ -58,6 +58,11 @@ class qdwf_solve_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class qdwf_request(ctypes.Structure):
+    _fields_ = [("act", qdwf_action), ("U", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("x_out", ctypes.c_void_p), ("params", qdwf_solve_params)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _SIG = {
@@ -78,6 +83,15 @@ _SIG = {
     "qdwf_solve": ([_P, _P, _P, _I, ctypes.POINTER(qdwf_solve_params),
                     ctypes.POINTER(qdwf_solve_stats), _P, _P], _I),
     "qdwf_geometry_tables": ([_P, _P, _P, _P], _I),
+    "qdwf_request_bytes": ([ctypes.POINTER(qdwf_action), ctypes.POINTER(qdwf_solve_params)],
+                           ctypes.c_size_t),
+    "qdwf_pool_create": ([_I, ctypes.c_size_t, _I, ctypes.POINTER(_P)], _I),
+    "qdwf_pool_destroy": ([_P], _I),
+    "qdwf_pool_submit": ([_P, ctypes.POINTER(qdwf_request), ctypes.POINTER(ctypes.c_uint64)], _I),
+    "qdwf_pool_step": ([_P, ctypes.POINTER(_I)], _I),
+    "qdwf_pool_poll": ([_P, ctypes.c_uint64, ctypes.POINTER(qdwf_solve_stats)], _I),
+    "qdwf_pool_info": ([_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
+                        ctypes.POINTER(_I), ctypes.POINTER(_I)], _I),
 }
 
 _lib = None
@@ -241,6 +255,56 @@ def qdwf_geometry_tables(ctx, V: int):
                                       nbr.ctypes.data_as(ctypes.c_void_p),
                                       sign.ctypes.data_as(ctypes.c_void_p)))
     return cb, nbr, sign
+
+
+def qdwf_request_bytes(act: qdwf_action, params: qdwf_solve_params) -> int:
+    return int(lib().qdwf_request_bytes(ctypes.byref(act), ctypes.byref(params)))
+
+
+def qdwf_pool_create(device: int, hbm_budget: int, max_slots: int):
+    h = ctypes.c_void_p()
+    _check(lib().qdwf_pool_create(int(device), ctypes.c_size_t(int(hbm_budget)), int(max_slots),
+                                  ctypes.byref(h)))
+    return h
+
+
+def qdwf_pool_destroy(pool):
+    _check(lib().qdwf_pool_destroy(pool))
+
+
+def qdwf_pool_submit(pool, act: qdwf_action, U, b, x_out, params: qdwf_solve_params) -> int:
+    r = qdwf_request()
+    r.act = act
+    r.U, r.b, r.x_out = _ptr(U, "U"), _ptr(b, "b"), _ptr(x_out, "x_out")
+    r.params = params
+    rid = ctypes.c_uint64()
+    _check(lib().qdwf_pool_submit(pool, ctypes.byref(r), ctypes.byref(rid)))
+    return int(rid.value)
+
+
+def qdwf_pool_step(pool) -> int:
+    n = ctypes.c_int()
+    _check(lib().qdwf_pool_step(pool, ctypes.byref(n)))
+    return int(n.value)
+
+
+def qdwf_pool_poll(pool, rid: int):
+    """(done, status, stats): done is False while the request is queued or running."""
+    st = qdwf_solve_stats()
+    rc = lib().qdwf_pool_poll(pool, ctypes.c_uint64(rid), ctypes.byref(st))
+    if rc == QDWF_EBUSY:
+        return False, rc, None
+    if rc not in (QDWF_OK, QDWF_ENOTCONV, QDWF_ENAN):
+        _check(rc)
+    return True, rc, st
+
+
+def qdwf_pool_info(pool):
+    a, b_ = ctypes.c_size_t(), ctypes.c_size_t()
+    na, nq = ctypes.c_int(), ctypes.c_int()
+    _check(lib().qdwf_pool_info(pool, ctypes.byref(a), ctypes.byref(b_), ctypes.byref(na),
+                                ctypes.byref(nq)))
+    return {"in_use": a.value, "peak": b_.value, "active": na.value, "queued": nq.value}
 
 
 def solve_params(system=QDWF_SYS_NORMAL_PC, inner_prec=QDWF_F64, layout=QDWF_RIRI, tol=1e-10,
