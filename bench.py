@@ -27,12 +27,26 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+# HBM bytes per launch of the FP32 full-D kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes scaled by a 2 GiB copy (profiles/hop_f32_riri_32x32x32x32x16.md),
+# keyed by the hash of the kernel source they were taken with; any other
+# source reports null until it is profiled again.
+MEASURED_TRAFFIC = {"54f2184ff810054d": 5.5455e9}
 FLOPS_PER_SITE = 1320        # Table 3 (real flops per 5D site per hop)
 MOBIUS = dict(M5=1.8, mf=0.01, b=1.5, c=0.5)
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hop.hip", "common.h"):
+        with open(os.path.join(HERE, "paper_2112_01852_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def time_launches(fn, steps, warmup, torch):
@@ -155,6 +169,102 @@ def solver_bench(args, torch, q, I):
     return out
 
 
+def multi_rhs_bench(args, torch, q, I):
+    """24 right-hand sides at 16^4 x 16 (12 point sources, one per spin and
+    colour at the origin, plus 12 Gaussian): batched eo hop and batched
+    mixed-precision solve of D x = b, against plain FP64 solves one at a time."""
+    L, Ls, nrhs = (16, 16, 16, 16), 16, 24
+    U = I.gauge_field(L, "haar", 4000)
+    srcs = [I.point_source(L, Ls, sp, c) for sp in range(4) for c in range(3)]
+    srcs += [I.gaussian_spinor(L, Ls, 4001 + j) for j in range(12)]
+    b = np.stack(srcs)
+    del srcs
+    D = q.Dirac(L, Ls, **MOBIUS)
+    D.set_gauge(U)
+    out = {}
+    # batched even-odd hop (links loaded once per tile for all 24 sources)
+    fin = D.pack(b, q.QDWF_F32, q.QDWF_RIRI, q.QDWF_ODD, nrhs)
+    fout = D.field(q.QDWF_F32, q.QDWF_EVEN, nrhs)
+    ms = time_launches(lambda: q.qdwf_apply_Deo(D.ctx, fout, fin, q.QDWF_EVEN, 0, q.QDWF_F32,
+                                                  q.QDWF_RIRI, nrhs), 10, 2, torch)
+    sites = D.n5h * nrhs
+    out["Deo_f32_nrhs24"] = {"ms": ms, "gflops": FLOPS_PER_SITE * sites / (ms * 1e-3) / 1e9,
+                             "algo_GBs": (48 + 144.0 / Ls / nrhs) * 4 * sites / (ms * 1e-3) / 1e9}
+    f1 = D.pack(b[12], q.QDWF_F32, q.QDWF_RIRI, q.QDWF_ODD, 1)
+    o1 = D.field(q.QDWF_F32, q.QDWF_EVEN, 1)
+    ms1 = time_launches(lambda: q.qdwf_apply_Deo(D.ctx, o1, f1, q.QDWF_EVEN, 0, q.QDWF_F32,
+                                                   q.QDWF_RIRI, 1), 10, 2, torch)
+    out["Deo_f32_nrhs1"] = {"ms": ms1, "gflops": FLOPS_PER_SITE * D.n5h / (ms1 * 1e-3) / 1e9}
+    log("multi-rhs hop", out)
+    del fin, fout, f1, o1
+    bf = D.pack(b, q.QDWF_F64, q.QDWF_RIRI, q.QDWF_FULL, nrhs)
+    x = D.field(q.QDWF_F64, q.QDWF_FULL, nrhs)
+    ws = D.workspace(q.QDWF_OP_SOLVE, q.QDWF_F32, nrhs)
+    prm = q.solve_params(system=q.QDWF_SYS_FULL, inner_prec=q.QDWF_F32, tol=1e-10,
+                         check_every=8, use_graph=1)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    rc, st = q.qdwf_solve(D.ctx, x, bf, nrhs, prm, ws)
+    dt = time.time() - t0
+    out["solve_batched_mixed_f32"] = {"rc": rc, "seconds": dt, "solves_per_s": nrhs / dt,
+                                      "iterations": st.iterations,
+                                      "full_residual": st.full_residual,
+                                      "converged": st.converged}
+    log("multi-rhs solve", out["solve_batched_mixed_f32"])
+    del x, ws, bf
+    torch.cuda.empty_cache()
+    # plain FP64 CG one source at a time (a sample of 3; solves/s extrapolates linearly)
+    ws = D.workspace(q.QDWF_OP_SOLVE, q.QDWF_F64, 1)
+    prm = q.solve_params(system=q.QDWF_SYS_FULL, inner_prec=q.QDWF_F64, tol=1e-10,
+                         check_every=8, use_graph=1)
+    times = []
+    for j in (0, 5, 12):
+        bj = D.pack(b[j], q.QDWF_F64, q.QDWF_RIRI, q.QDWF_FULL, 1)
+        xj = D.field(q.QDWF_F64, q.QDWF_FULL, 1)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        rc1, st1 = q.qdwf_solve(D.ctx, xj, bj, 1, prm, ws)
+        times.append(time.time() - t0)
+    out["solve_sequential_f64"] = {"sampled_sources": 3, "mean_seconds": float(np.mean(times)),
+                                   "solves_per_s": 1.0 / float(np.mean(times))}
+    log("sequential fp64", out["solve_sequential_f64"])
+    D.close()
+    return out
+
+
+def serving_bench(args, torch, q):
+    """Poisson stream of mixed-precision even-odd Mobius solves through the
+    pool (volume 8^4..24^4, Ls 8/12/16, mf log-uniform [1e-3, 1e-1])."""
+    from paper_2112_01852_amd import serve
+    n = args.serve_requests
+    specs = serve.make_specs(n, 5000)
+    prepared = serve.prepare(specs)
+    prm_mixed = q.solve_params(inner_prec=q.QDWF_F16, layout=q.QDWF_RIRI, tol=1e-10,
+                               check_every=8, use_graph=0)
+    prm_plain = q.solve_params(inner_prec=q.QDWF_F64, layout=q.QDWF_RIRI, tol=1e-10,
+                               check_every=8, use_graph=1)
+    # isolated service times (plain FP64) give the offered load and the FIFO baseline
+    t_plain = []
+    for p in prepared:
+        rc, st, dt, _ = serve.solo_solve(p, prm_plain)
+        t_plain.append(dt)
+    mean_s = float(np.mean(t_plain))
+    rate = args.serve_load / mean_s
+    arrivals = serve.poisson_arrivals(n, rate, 5001)
+    budget = int(args.serve_budget_gb * 2**30)
+    res = serve.run_pool(prepared, arrivals, prm_mixed, budget, max_slots=8)
+    base_lat, base_end = serve.fifo_baseline(t_plain, arrivals)
+    ok = sum(1 for s in res["status"] if s == q.QDWF_OK)
+    out = {"requests": n, "offered_load_vs_fp64": args.serve_load, "arrival_rate_per_s": rate,
+           "budget_bytes": budget, "peak_bytes": res["peak_bytes"], "converged": ok,
+           "served_mixed": {**serve.percentiles(res["latency"]),
+                            "solves_per_s": n / res["makespan"]},
+           "fifo_plain_fp64": {**serve.percentiles(base_lat), "solves_per_s": n / base_end,
+                               "mean_service_s": mean_s}}
+    log("serving", out)
+    return out
+
+
 def cpu_baseline():
     """FP64 oracle (plain C++ loops, OpenMP) applying the same operator to a
     16^4 x 16 lattice: 1/16 of the 32^4 x 16 workload's 5D volume."""
@@ -187,6 +297,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-solver", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=24)
+    ap.add_argument("--serve-load", type=float, default=0.9,
+                    help="offered load relative to one-at-a-time plain FP64 service")
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--variants", default="",
                     help="comma list of Dslash variants to time (default all), e.g. f32_riri")
     args = ap.parse_args()
@@ -206,6 +322,8 @@ def main():
     best_layout = best.split("_")[-1]
     head = dres[best]
     solver = None if args.no_solver else solver_bench(args, torch, q, I)
+    multi = None if args.no_multi else multi_rhs_bench(args, torch, q, I)
+    served = None if args.no_serve else serving_bench(args, torch, q)
     cpub = None if args.no_cpu else cpu_baseline()
     line = {
         "metric": "Dslash GFlop/s+HBM GB/s (32^4xLs16); mixed-prec CG solves/s, p50/p99 latency",
@@ -226,10 +344,16 @@ def main():
                    "sites_5d": sites, "parallelism": "single GPU"},
         "hbm_GBs_algorithmic": head["algo_GBs"],
         "roofline": {"bound": "hbm", "achieved": head["algo_GBs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": head["algo_GBs"] / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": head["algo_GBs"] / HBM_PEAK_GBS,
+                     "traffic": (MEASURED_TRAFFIC.get(kernel_source_hash())
+                                 if best_layout == "riri" else None),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "algorithmic_bytes": algorithmic_bytes_per_site(4, 16, False) * sites},
         "attainable_hbm": probe,
         "dslash": dres,
         "solver_24x24x24x24x16": solver,
+        "multi_rhs_16x16x16x16x16_n24": multi,
+        "serving": served,
         "cpu_baseline": cpub,
     }
     print(json.dumps(line), flush=True)

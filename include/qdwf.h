@@ -93,6 +93,7 @@ extern "C" {
 #define QDWF_OP_MDAGM   1
 #define QDWF_OP_SOLVE   2
 #define QDWF_OP_REDUCE  3
+#define QDWF_OP_TUNE    4
 
 /* ---- types ------------------------------------------------------------ */
 typedef struct {
@@ -215,6 +216,21 @@ int qdwf_dot(qdwf_ctx* ctx, double* out, const void* x, const void* y, int subse
  * Returns QDWF_ENOTCONV if max_iter is reached, QDWF_ENAN on NaN/Inf. */
 int qdwf_solve(qdwf_ctx* ctx, void* x, const void* b, int nrhs, const qdwf_solve_params* params,
                qdwf_solve_stats* stats, void* ws, void* stream);
+
+/* ---- autotuner -------------------------------------------------------- */
+/* Times every launch shape of the hop kernel (threads per block, right-hand
+ * sides per block, XCD-aware block order, LDS reservation capping resident
+ * blocks per CU) on D and D^dag for (prec, layout, nrhs) and keeps the fastest
+ * for this context; later calls of every operator with that precision,
+ * layout and nrhs use it. If the environment variable QDWF_TUNE_CACHE names a
+ * file, results are appended to it and contexts of the same shape created
+ * later pick them up. ws: qdwf_workspace_bytes(ctx, QDWF_OP_TUNE, prec, nrhs)
+ * bytes (overwritten). best_ms (may be NULL) receives 2 doubles: the best
+ * D and D^dag times. Synchronous. */
+int qdwf_tune(qdwf_ctx* ctx, int prec, int layout, int nrhs, void* ws, void* stream,
+              double* best_ms);
+/* The shape the operators will use: {threads, nrhs per block, xcd order, lds reservation}. */
+int qdwf_tuned_shape(qdwf_ctx* ctx, int prec, int layout, int dagger, int nrhs, int32_t* shape4);
 
 /* ---- serving pool ----------------------------------------------------- */
 /* Continuous batching of independent solves of M_pc^dag M_pc x_o = b_o, each

@@ -237,6 +237,7 @@ int qdwf_create(const qdwf_action* act, int device, qdwf_ctx** out) {
 
 int qdwf_destroy(qdwf_ctx* ctx) {
   if (!ctx) return QDWF_OK;
+  forget_tuning(ctx);
   DeviceGuard dg(ctx->device);
   if (ctx->d_nbr) (void)hipFree(ctx->d_nbr);
   if (ctx->d_site_lex) (void)hipFree(ctx->d_site_lex);
@@ -375,6 +376,7 @@ size_t qdwf_workspace_bytes(const qdwf_ctx* ctx, int op, int prec, int nrhs) {
     case QDWF_OP_MDAGM: return 3 * al;
     case QDWF_OP_SOLVE: return solve_ws_bytes(ctx, prec, nrhs, 0);
     case QDWF_OP_REDUCE: return dot_ws_bytes((long)ctx->g.n5h * 24 * 2, nrhs);
+    case QDWF_OP_TUNE: return 2 * ((2 * half + 255) & ~(size_t)255);
   }
   return 0;
 }

@@ -176,5 +176,6 @@ int launch_pack_links(qdwf_ctx* ctx, const void* U, int canon_prec, hipStream_t 
 // Default hop launch shape and tuner cache lookup.
 HopShape default_shape(const qdwf_ctx* ctx, int prec, int nrhs);
 bool tuned_shape(const qdwf_ctx* ctx, int prec, int layout, int dagger, int nrhs, HopShape* out);
+void forget_tuning(const qdwf_ctx* ctx);
 
 }  // namespace qdwf

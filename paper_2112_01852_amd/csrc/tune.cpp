@@ -1,8 +1,212 @@
-// Launch-shape cache for the hop kernel (filled by the autotuner).
+// Autotuner for the hop kernel's launch shape.
+//
+// For a context, precision, layout and number of right-hand sides, every
+// candidate shape -- threads per block, right-hand sides per block, XCD-aware
+// block order on/off, and an LDS reservation that caps how many blocks share
+// a CU -- is timed with HIP events on the full operator D and on D^dag, and
+// the fastest is kept in the context. With QDWF_TUNE_CACHE naming a file, the
+// results are appended there (one JSON object per line, keyed by lattice, Ls,
+// precision, layout, dagger, nrhs and device architecture) and read back when
+// a context of the same shape is created, so tuning happens once per machine.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
 #include "common.h"
 
 namespace qdwf {
 
-bool tuned_shape(const qdwf_ctx*, int, int, int, int, HopShape*) { return false; }
+namespace {
+
+typedef std::tuple<int, int, int, int> TuneKey;   // prec, layout, dagger, nrhs
+
+std::mutex g_mu;
+std::map<const qdwf_ctx*, std::map<TuneKey, HopShape>> g_tuned;
+std::map<const qdwf_ctx*, bool> g_loaded;   // cache file read for this context
+
+std::string arch_name(int device) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, device) != hipSuccess) return "unknown";
+  std::string s = p.gcnArchName;
+  const size_t c = s.find(':');
+  return c == std::string::npos ? s : s.substr(0, c);
+}
+
+std::string cache_key(const qdwf_ctx* c, int prec, int layout, int dagger, int nrhs) {
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%dx%dx%dx%d_Ls%d_p%d_l%d_d%d_n%d_t%d.%d.%d_%s", c->g.L[0], c->g.L[1],
+           c->g.L[2], c->g.L[3], c->g.Ls, prec, layout, dagger, nrhs, c->tile[0], c->tile[1],
+           c->tile[2], arch_name(c->device).c_str());
+  return buf;
+}
+
+void cache_store(const std::string& key, const HopShape& s, double ms) {
+  const char* path = std::getenv("QDWF_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"nrb\": %d, \"xcd\": %d, \"lds_pad\": %d, \"ms\": %.6f}\n",
+               key.c_str(), s.threads, s.nrb, s.xcd, s.lds_pad, ms);
+  std::fclose(f);
+}
+
+bool cache_load(const std::string& key, HopShape* out) {
+  const char* path = std::getenv("QDWF_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    char k[256];
+    HopShape s;
+    double ms;
+    if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"threads\": %d, \"nrb\": %d, \"xcd\": %d, \"lds_pad\": %d, \"ms\": %lf}",
+                    k, &s.threads, &s.nrb, &s.xcd, &s.lds_pad, &ms) == 6 &&
+        key == k) {
+      *out = s;   // the last entry for a key wins
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+}  // namespace
+
+bool tuned_shape(const qdwf_ctx* ctx, int prec, int layout, int dagger, int nrhs, HopShape* out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_loaded[ctx]) {
+    // first use of this context: take every cached entry that matches it
+    g_loaded[ctx] = true;
+    const char* path = std::getenv("QDWF_TUNE_CACHE");
+    if (path && *path)
+    for (int p = QDWF_F64; p <= QDWF_BF16; ++p)
+      for (int l = 0; l < 2; ++l)
+        for (int d = 0; d < 2; ++d)
+          for (int n : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32}) {
+            HopShape s;
+            if (cache_load(cache_key(ctx, p, l, d, n), &s)) g_tuned[ctx][TuneKey(p, l, d, n)] = s;
+          }
+  }
+  auto it = g_tuned.find(ctx);
+  if (it != g_tuned.end()) {
+    auto jt = it->second.find(TuneKey(prec, layout, dagger, nrhs));
+    if (jt != it->second.end()) {
+      *out = jt->second;
+      return true;
+    }
+  }
+  return false;
+}
+
+void forget_tuning(const qdwf_ctx* ctx) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_tuned.erase(ctx);
+  g_loaded.erase(ctx);
+}
 
 }  // namespace qdwf
+
+using namespace qdwf;
+
+extern "C" {
+
+int qdwf_tune(qdwf_ctx* ctx, int prec, int layout, int nrhs, void* ws, void* stream,
+              double* best_ms) {
+  if (!ctx || !ws) return fail(QDWF_EINVAL, "null argument");
+  if (prec < QDWF_F64 || prec > QDWF_BF16) return fail(QDWF_EINVAL, "unknown precision %d", prec);
+  if (layout != QDWF_RIRI && layout != QDWF_RRII) return fail(QDWF_EINVAL, "unknown layout %d", layout);
+  if (nrhs < 1 || nrhs > 4096) return fail(QDWF_EINVAL, "nrhs out of range");
+  if (!ctx->gauge_set) return fail(QDWF_EINVAL, "gauge field not set");
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const long half = ctx->g.n5h * 24;
+  const size_t field = (size_t)2 * half * nrhs * prec_bytes(prec);
+  char* in = reinterpret_cast<char*>(ws);
+  char* out = in + ((field + 255) & ~(size_t)255);
+  QDWF_HIP(hipMemsetAsync(in, 0, field, st));
+  const double al = ctx->act.b * (4.0 - ctx->act.M5) + 1.0;
+  const double be = ctx->act.c * (4.0 - ctx->act.M5) - 1.0;
+  const size_t bytes = prec_bytes(prec);
+  HopArgs a = {};
+  a.in[0] = in + half * bytes;
+  a.in[1] = in;
+  a.out[0] = out;
+  a.out[1] = out + half * bytes;
+  a.z[0] = in;
+  a.z[1] = in + half * bytes;
+  a.rs_in = a.rs_out = a.rs_z = 2 * half;
+  a.par0 = 0;
+  a.npar = 2;
+  a.nrhs = nrhs;
+  a.epi = 1;
+  a.hop_scale = -0.5;
+  a.alpha = al;
+  a.beta = be;
+  hipEvent_t e0, e1;
+  QDWF_HIP(hipEventCreate(&e0));
+  QDWF_HIP(hipEventCreate(&e1));
+  const int gpw = 64 / ctx->g.Ls;
+  const int reps = 5;
+  for (int dagger = 0; dagger < 2; ++dagger) {
+    HopShape best = default_shape(ctx, prec, nrhs);
+    double best_t = 1e30;
+    for (int waves = 1; waves <= 4; ++waves) {
+      const int G = waves * gpw;
+      if (G > 32 || G < 1) continue;
+      for (int nrb = 1; nrb <= G; ++nrb) {
+        if (G % nrb || nrb > nrhs || (nrb > 1 && G / nrb < 2)) continue;
+        for (int xcd = 0; xcd < 2; ++xcd)
+          for (int pad : {0, 24 * 1024, 44 * 1024}) {
+            HopShape s = {64 * waves, nrb, xcd, pad};
+            // warm-up launch; shapes the kernel rejects (LDS) are skipped
+            if (launch_hop(ctx, prec, layout, dagger, a, st, &s) != QDWF_OK) continue;
+            QDWF_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < reps; ++r) launch_hop(ctx, prec, layout, dagger, a, st, &s);
+            QDWF_HIP(hipEventRecord(e1, st));
+            QDWF_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            QDWF_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms / reps < best_t) {
+              best_t = ms / reps;
+              best = s;
+            }
+          }
+      }
+    }
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      g_tuned[ctx][TuneKey(prec, layout, dagger, nrhs)] = best;
+    }
+    cache_store(cache_key(ctx, prec, layout, dagger, nrhs), best, best_t);
+    if (best_ms) best_ms[dagger] = best_t;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  set_error("");
+  if (prev >= 0) (void)hipSetDevice(prev);
+  return QDWF_OK;
+}
+
+int qdwf_tuned_shape(qdwf_ctx* ctx, int prec, int layout, int dagger, int nrhs, int32_t* shape4) {
+  if (!ctx || !shape4) return fail(QDWF_EINVAL, "null argument");
+  HopShape s;
+  if (!tuned_shape(ctx, prec, layout, dagger, nrhs, &s)) s = default_shape(ctx, prec, nrhs);
+  shape4[0] = s.threads;
+  shape4[1] = s.nrb;
+  shape4[2] = s.xcd;
+  shape4[3] = s.lds_pad;
+  return QDWF_OK;
+}
+
+}  // extern "C"

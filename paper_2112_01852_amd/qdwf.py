@@ -21,7 +21,7 @@ QDWF_RRII, QDWF_RIRI = 0, 1
 QDWF_EVEN, QDWF_ODD, QDWF_FULL = 0, 1, 2
 QDWF_MEE_FWD, QDWF_MEE_INV = 0, 1
 QDWF_SYS_NORMAL_PC, QDWF_SYS_FULL = 0, 1
-QDWF_OP_MPC, QDWF_OP_MDAGM, QDWF_OP_SOLVE, QDWF_OP_REDUCE = 0, 1, 2, 3
+QDWF_OP_MPC, QDWF_OP_MDAGM, QDWF_OP_SOLVE, QDWF_OP_REDUCE, QDWF_OP_TUNE = 0, 1, 2, 3, 4
 
 TORCH_DTYPE = {QDWF_F64: torch.float64, QDWF_F32: torch.float32,
                QDWF_F16: torch.float16, QDWF_BF16: torch.bfloat16}
@@ -83,6 +83,8 @@ _SIG = {
     "qdwf_solve": ([_P, _P, _P, _I, ctypes.POINTER(qdwf_solve_params),
                     ctypes.POINTER(qdwf_solve_stats), _P, _P], _I),
     "qdwf_geometry_tables": ([_P, _P, _P, _P], _I),
+    "qdwf_tune": ([_P, _I, _I, _I, _P, _P, _P], _I),
+    "qdwf_tuned_shape": ([_P, _I, _I, _I, _I, _P], _I),
     "qdwf_request_bytes": ([ctypes.POINTER(qdwf_action), ctypes.POINTER(qdwf_solve_params)],
                            ctypes.c_size_t),
     "qdwf_pool_create": ([_I, ctypes.c_size_t, _I, ctypes.POINTER(_P)], _I),
@@ -255,6 +257,21 @@ def qdwf_geometry_tables(ctx, V: int):
                                       nbr.ctypes.data_as(ctypes.c_void_p),
                                       sign.ctypes.data_as(ctypes.c_void_p)))
     return cb, nbr, sign
+
+
+def qdwf_tune(ctx, prec, layout, nrhs, ws, stream=None):
+    """Tunes the hop launch shape; returns (best D ms, best D^dag ms)."""
+    best = (ctypes.c_double * 2)()
+    _check(lib().qdwf_tune(ctx, int(prec), int(layout), int(nrhs), _ptr(ws, "ws"), _stream(stream),
+                           ctypes.cast(best, ctypes.c_void_p)))
+    return best[0], best[1]
+
+
+def qdwf_tuned_shape(ctx, prec, layout, dagger, nrhs):
+    out = (ctypes.c_int32 * 4)()
+    _check(lib().qdwf_tuned_shape(ctx, int(prec), int(layout), int(dagger), int(nrhs),
+                                  ctypes.cast(out, ctypes.c_void_p)))
+    return dict(threads=out[0], nrb=out[1], xcd=out[2], lds_pad=out[3])
 
 
 def qdwf_request_bytes(act: qdwf_action, params: qdwf_solve_params) -> int:
