@@ -267,11 +267,11 @@ def serving_bench(args, torch, q):
 
 def cpu_baseline():
     """FP64 oracle (plain C++ loops, OpenMP) applying the same operator to a
-    16^4 x 16 lattice: 1/16 of the 32^4 x 16 workload's 5D volume."""
+    24^4 x 16 lattice: 0.32 of the 32^4 x 16 workload's 5D volume."""
     from oracle import cpu
     from paper_2112_01852_amd import inputs as I
     cpu.build(force=False)
-    L, Ls = (16, 16, 16, 16), 16
+    L, Ls = (24, 24, 24, 24), 16
     a = cpu.Action(L=L, Ls=Ls, **MOBIUS)
     U = I.gauge_field(L, "haar", 2000)
     psi = I.gaussian_spinor(L, Ls, 2001)
@@ -286,8 +286,8 @@ def cpu_baseline():
     threads = int(os.environ.get("OMP_NUM_THREADS", cores))
     return {"value": FLOPS_PER_SITE * sites / dt / 1e9, "unit": "GFlop/s", "cores": min(cores, threads),
             "kind": "oracle", "seconds": dt,
-            "sample": "FP64 oracle D_dwf (Mobius b=1.5 c=0.5) on a 16^4 x Ls16 lattice, "
-                      "1/16 of the 32^4 x 16 5D volume; GFlop/s with 1320 flops per 5D site"}
+            "sample": "FP64 oracle D_dwf (Mobius b=1.5 c=0.5) on a 24^4 x Ls16 lattice, "
+                      "0.32 of the 32^4 x 16 5D volume; GFlop/s with 1320 flops per 5D site"}
 
 
 def main():

@@ -22,6 +22,7 @@
 #include <cstdlib>
 
 #include "common.h"
+#include "siteio.h"
 
 namespace qdwf {
 
@@ -46,106 +47,6 @@ __device__ inline int xcd_remap(int bid, int nb) {
   const int x = bid & 7, k = bid >> 3;
   return (x < rem) ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
 }
-
-// ------------------------------------------------------------ site I/O
-// Register order of the 24 reals of a site: v[(spin*3 + colour)*2 + re/im].
-template <class S, int LAYOUT> struct SiteIO;
-
-template <class S> struct SiteIO<S, QDWF_RRII> {
-  typedef typename Store<S>::compute T;
-  __device__ static inline void load(const S* __restrict__ f, long j, long plane, T* v) {
-#pragma unroll
-    for (int sc = 0; sc < 12; ++sc) {
-      v[2 * sc] = Store<S>::to(f[(long)sc * plane + j]);
-      v[2 * sc + 1] = Store<S>::to(f[(long)(12 + sc) * plane + j]);
-    }
-  }
-  __device__ static inline void store(S* __restrict__ f, long j, long plane, const T* v) {
-#pragma unroll
-    for (int sc = 0; sc < 12; ++sc) {
-      f[(long)sc * plane + j] = Store<S>::from(v[2 * sc]);
-      f[(long)(12 + sc) * plane + j] = Store<S>::from(v[2 * sc + 1]);
-    }
-  }
-};
-
-template <> struct SiteIO<double, QDWF_RIRI> {
-  __device__ static inline void load(const double* __restrict__ f, long j, long, double* v) {
-    const double2* p = reinterpret_cast<const double2*>(f + j * 24);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) {
-      const double2 q = p[k];
-      v[2 * k] = q.x;
-      v[2 * k + 1] = q.y;
-    }
-  }
-  __device__ static inline void store(double* __restrict__ f, long j, long, const double* v) {
-    double2* p = reinterpret_cast<double2*>(f + j * 24);
-#pragma unroll
-    for (int k = 0; k < 12; ++k) p[k] = make_double2(v[2 * k], v[2 * k + 1]);
-  }
-};
-
-template <> struct SiteIO<float, QDWF_RIRI> {
-  __device__ static inline void load(const float* __restrict__ f, long j, long, float* v) {
-    const float4* p = reinterpret_cast<const float4*>(f + j * 24);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const float4 q = p[k];
-      v[4 * k] = q.x;
-      v[4 * k + 1] = q.y;
-      v[4 * k + 2] = q.z;
-      v[4 * k + 3] = q.w;
-    }
-  }
-  __device__ static inline void store(float* __restrict__ f, long j, long, const float* v) {
-    float4* p = reinterpret_cast<float4*>(f + j * 24);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) p[k] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
-  }
-};
-
-// 16-bit storage: 24 reals = 48 bytes = 3 x 16-byte loads.
-template <class S> struct SiteIO16 {
-  __device__ static inline void load(const S* __restrict__ f, long j, long, float* v) {
-    const uint4* p = reinterpret_cast<const uint4*>(f + j * 24);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const uint4 q = p[k];
-      const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        v[8 * k + 2 * m] = Store<S>::to(bits<S>((uint16_t)(w[m] & 0xffffu)));
-        v[8 * k + 2 * m + 1] = Store<S>::to(bits<S>((uint16_t)(w[m] >> 16)));
-      }
-    }
-  }
-  __device__ static inline void store(S* __restrict__ f, long j, long, const float* v) {
-    uint4* p = reinterpret_cast<uint4*>(f + j * 24);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      uint32_t w[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m)
-        w[m] = (uint32_t)raw(Store<S>::from(v[8 * k + 2 * m])) |
-               ((uint32_t)raw(Store<S>::from(v[8 * k + 2 * m + 1])) << 16);
-      p[k] = make_uint4(w[0], w[1], w[2], w[3]);
-    }
-  }
-  template <class X> __device__ static inline X bits(uint16_t u);
-  __device__ static inline uint16_t raw(_Float16 h) { return __builtin_bit_cast(uint16_t, h); }
-  __device__ static inline uint16_t raw(bf16 h) { return h.u; }
-};
-template <> template <> __device__ inline _Float16 SiteIO16<_Float16>::bits<_Float16>(uint16_t u) {
-  return __builtin_bit_cast(_Float16, u);
-}
-template <> template <> __device__ inline bf16 SiteIO16<bf16>::bits<bf16>(uint16_t u) {
-  bf16 r;
-  r.u = u;
-  return r;
-}
-template <> struct SiteIO<_Float16, QDWF_RIRI> : SiteIO16<_Float16> {};
-template <> struct SiteIO<bf16, QDWF_RIRI> : SiteIO16<bf16> {};
 
 // ----------------------------------------------- spin projection algebra
 // The constants below are compile-time, and every case is written out so that
@@ -401,7 +302,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_ker
   }
   __syncthreads();
 
-  const int Ls = k.Ls;
+  const int Ls = DPP16 ? 16 : k.Ls;   // a constant on the Ls = 16 path
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int gl = lane / Ls, s = lane - gl * Ls;
   const bool lane_ok = gl < k.gpw;
@@ -415,8 +316,8 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_ker
   const int* nbs = snb + sl;
 
   T va[24], vb[24];   // two neighbour spinors in flight
-  SiteIO<S, LAYOUT>::load(in, (long)nbs[0] * Ls + s, k.plane, va);
-  SiteIO<S, LAYOUT>::load(in, (long)nbs[k.nsb] * Ls + s, k.plane, vb);
+  SiteIO<S, LAYOUT>::load(in, nbs[0], s, Ls, k.plane, va);
+  SiteIO<S, LAYOUT>::load(in, nbs[k.nsb], s, Ls, k.plane, vb);
 
   {
     // one thread per link: 18 contiguous reals, loaded with vector loads
@@ -463,7 +364,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_ker
 #pragma unroll
     for (int i = 0; i < 24; ++i) v[i] = buf[i];
     if constexpr (D < 6)
-      SiteIO<S, LAYOUT>::load(in, (long)nbs[(D + 2) * k.nsb] * Ls + s, k.plane, buf);
+      SiteIO<S, LAYOUT>::load(in, nbs[(D + 2) * k.nsb], s, Ls, k.plane, buf);
     if constexpr (!DAG) {
       // chi / b = psi + (c/b) (P+ psi_{s-1} + P- psi_{s+1}), walls included
 #pragma unroll
@@ -492,11 +393,10 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_ker
     for (int i = 0; i < 24; ++i) acc[i] = tmp[i];
   }
   const T hs = (T)k.hop_scale_b;   // hop scale times b
-  const long j = (long)cbc * Ls + s;
   if (k.epi) {
     const S* zf = reinterpret_cast<const S*>(k.z[p]) + (long)rc * k.rs_z;
     T z[24];
-    SiteIO<S, LAYOUT>::load(zf, j, k.plane, z);
+    SiteIO<S, LAYOUT>::load(zf, cbc, s, Ls, k.plane, z);
     const T al = (T)k.alpha, be = (T)k.beta;
     const T bm = be * wm, bp = be * wp;
 #pragma unroll
@@ -518,7 +418,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_ker
   }
   if (active) {
     S* out = reinterpret_cast<S*>(k.out[p]) + (long)rc * k.rs_out;
-    SiteIO<S, LAYOUT>::store(out, j, k.plane, acc);
+    SiteIO<S, LAYOUT>::store(out, cbc, s, Ls, k.plane, acc);
   }
 }
 

@@ -12,32 +12,11 @@
 #include <cmath>
 
 #include "common.h"
+#include "siteio.h"
 
 namespace qdwf {
 
 namespace {
-
-template <class S, int LAYOUT>
-__device__ inline void ld(const S* f, long j, long plane, typename Store<S>::compute* v) {
-  if (LAYOUT == QDWF_RIRI) {
-#pragma unroll
-    for (int c = 0; c < 24; ++c) v[c] = Store<S>::to(f[j * 24 + c]);
-  } else {
-#pragma unroll
-    for (int c = 0; c < 24; ++c) v[c] = Store<S>::to(f[(long)((c & 1) * 12 + (c >> 1)) * plane + j]);
-  }
-}
-
-template <class S, int LAYOUT>
-__device__ inline void st(S* f, long j, long plane, const typename Store<S>::compute* v) {
-  if (LAYOUT == QDWF_RIRI) {
-#pragma unroll
-    for (int c = 0; c < 24; ++c) f[j * 24 + c] = Store<S>::from(v[c]);
-  } else {
-#pragma unroll
-    for (int c = 0; c < 24; ++c) f[(long)((c & 1) * 12 + (c >> 1)) * plane + j] = Store<S>::from(v[c]);
-  }
-}
 
 // grid: x = site blocks, y = half index * nrhs + rhs
 template <class S, int LAYOUT>
@@ -62,10 +41,9 @@ __global__ void __launch_bounds__(256) local_kernel(const S* in, S* out,
   const int cbc = min(cb, Vh - 1);
   const int h = blockIdx.y % nhalf, r = blockIdx.y / nhalf;
   const long off = (long)r * rs + (long)h * rs_half;
-  const long j = (long)cbc * Ls + s;
 
   T v[24];
-  ld<S, LAYOUT>(in + off, j, plane, v);
+  SiteIO<S, LAYOUT>::load(in + off, cbc, s, Ls, plane, v);
   if (lane_ok) {
 #pragma unroll
     for (int c = 0; c < 24; ++c) col[(gid * Ls + s) * 24 + c] = v[c];
@@ -85,7 +63,7 @@ __global__ void __launch_bounds__(256) local_kernel(const S* in, S* out,
 #pragma unroll
     for (int c = 12; c < 24; ++c) o[c] += b * cg[t * 24 + c];
   }
-  st<S, LAYOUT>(out + off, j, plane, o);
+  SiteIO<S, LAYOUT>::store(out + off, cbc, s, Ls, plane, o);
 }
 
 }  // namespace

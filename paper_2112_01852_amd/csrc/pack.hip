@@ -1,14 +1,17 @@
 // Layout conversion between the canonical caller-facing arrays and the
 // internal even-odd fields, and packing of the gauge links.
 //
-// Internal spinor half field (one parity): 5D site j = i*Ls + s where i is the
+// Internal spinor half field (one parity): 5D site (i, s) where i is the
 // site's index in the library's traversal order of that parity; the 24 reals
-// of a site are interleaved complex (RIRI) or split into 24 planes of length
-// (V/2)*Ls ordered [re/im][spin][colour] (RRII). Links: [parity][mu][cb][18]
+// of a site are interleaved complex, blocked over the Ls slices of a 4D site
+// in chunks of 4 reals (RIRI), or split into 24 planes of length (V/2)*Ls
+// ordered [re/im][spin][colour] (RRII); the offsets are in siteio.h.
+// Links: [parity][mu][cb][18]
 // (3x3 complex row-major, interleaved), with the boundary factor bc[mu]
 // multiplied into U_mu(x) on the last slice x_mu = L_mu - 1, which is the one
 // link used by both hops that cross that boundary.
 #include "common.h"
+#include "siteio.h"
 
 namespace qdwf {
 
@@ -19,7 +22,6 @@ template <class R, class S, int LAYOUT, bool UNPACK>
 __global__ void pack_kernel(const void* __restrict__ src_v, void* __restrict__ dst_v, int nhalf,
                             int par0, long n5h, int Ls, int V, const int* __restrict__ site_lex,
                             int Vh, int nrhs) {
-  typedef typename Store<S>::compute T;
   const long total = (long)nrhs * nhalf * n5h;
   for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (long)gridDim.x * blockDim.x) {
@@ -38,16 +40,16 @@ __global__ void pack_kernel(const void* __restrict__ src_v, void* __restrict__ d
 #pragma unroll
       for (int c = 0; c < 24; ++c) {
         const S v = Store<S>::from64((double)src[c]);
-        if (LAYOUT == QDWF_RIRI) dst[j * 24 + c] = v;
-        else dst[(long)((c & 1) * 12 + (c >> 1)) * n5h + j] = v;
+        if (LAYOUT == QDWF_RIRI) dst[riri_offset(cb, s, c, Ls)] = v;
+        else dst[rrii_offset(cb, s, c, Ls, n5h)] = v;
       }
     } else {
       const S* src = reinterpret_cast<const S*>(src_v) + ibase;
       R* dst = reinterpret_cast<R*>(dst_v) + cidx;
 #pragma unroll
       for (int c = 0; c < 24; ++c) {
-        const S v = (LAYOUT == QDWF_RIRI) ? src[j * 24 + c]
-                                          : src[(long)((c & 1) * 12 + (c >> 1)) * n5h + j];
+        const S v = (LAYOUT == QDWF_RIRI) ? src[riri_offset(cb, s, c, Ls)]
+                                          : src[rrii_offset(cb, s, c, Ls, n5h)];
         dst[c] = (R)Store<S>::to(v);
       }
     }

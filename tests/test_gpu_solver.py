@@ -66,6 +66,11 @@ def test_solve_normal_pc(setup, inner, layout):
     assert _rel(x, x_ref) <= 1e-8
     if inner != 0:
         assert st.reliable_updates >= 1
+        # the inner iteration must track the FP64 one: an inner operator that
+        # disagreed with the outer one would still end at the true residual,
+        # but only after many restarts
+        rc0, st0, _ = _solve(q, D, b, 0, layout)
+        assert st.iterations <= 1.5 * st0.iterations + 10, (st.iterations, st0.iterations)
 
 
 def test_multi_rhs_solve_matches_single(setup):
