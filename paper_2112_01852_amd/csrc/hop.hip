@@ -239,29 +239,43 @@ template <class S> struct LinkIO {
 
 template <int N> struct IC { static constexpr int value = N; };
 
-// Values of the lanes holding slices s-1 and s+1 of the same (site, rhs)
-// group. With Ls = 16 a group is one 16-lane DPP row and the exchange is a
-// row rotate (no LDS round trip); otherwise a cross-lane permute.
-__device__ inline int dpp_ror1(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x121, 0xF, 0xF, false); }
-__device__ inline int dpp_ror15(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x12F, 0xF, 0xF, false); }
+// s +- 1 exchange inside a group of Ls lanes. fm(c, x, a) = a + c x(s-1) and
+// fp(c, x, a) = a + c x(s+1), cyclically in s (the walls are handled by the
+// caller's coefficients). Generic Ls uses cross-lane permutes.
 template <bool DPP16> struct SShift {
   int src_m, src_p;
-  template <class T> __device__ inline T m(T v) const { return __shfl(v, src_m, 64); }
-  template <class T> __device__ inline T p(T v) const { return __shfl(v, src_p, 64); }
+  template <class T> __device__ inline T fm(T c, T x, T a) const { return fmac(c, (T)__shfl(x, src_m, 64), a); }
+  template <class T> __device__ inline T fp(T c, T x, T a) const { return fmac(c, (T)__shfl(x, src_p, 64), a); }
 };
+
+// Ls = 16: a group is one DPP row and the exchange is a row rotate. In FP32
+// the rotate is the source modifier of the FMA itself (one instruction); the
+// s_nop covers the two wait states a DPP read needs after a VALU write of the
+// same register, which the compiler does not track through inline assembly.
+// FP64 has no row rotate on 64-bit operands, so each half is moved first.
+__device__ inline int dpp_ror1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x121, 0xF, 0xF, false); }
+__device__ inline int dpp_ror15(int v) { return __builtin_amdgcn_mov_dpp(v, 0x12F, 0xF, 0xF, false); }
 template <> struct SShift<true> {
   int src_m, src_p;
-  __device__ inline float m(float v) const { return __int_as_float(dpp_ror1(__float_as_int(v))); }
-  __device__ inline float p(float v) const { return __int_as_float(dpp_ror15(__float_as_int(v))); }
-  __device__ inline double m(double v) const {
-    const long long b = __double_as_longlong(v);
-    const int lo = dpp_ror1((int)b), hi = dpp_ror1((int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+  __device__ inline float fm(float c, float x, float a) const {
+    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_ror:1 row_mask:0xf bank_mask:0xf"
+        : "+v"(a) : "v"(x), "v"(c));
+    return a;
   }
-  __device__ inline double p(double v) const {
-    const long long b = __double_as_longlong(v);
+  __device__ inline float fp(float c, float x, float a) const {
+    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_ror:15 row_mask:0xf bank_mask:0xf"
+        : "+v"(a) : "v"(x), "v"(c));
+    return a;
+  }
+  __device__ inline double fm(double c, double x, double a) const {
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_ror1((int)b), hi = dpp_ror1((int)(b >> 32));
+    return fmac(c, __longlong_as_double(((long long)hi << 32) | (unsigned int)lo), a);
+  }
+  __device__ inline double fp(double c, double x, double a) const {
+    const long long b = __double_as_longlong(x);
     const int lo = dpp_ror15((int)b), hi = dpp_ror15((int)(b >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    return fmac(c, __longlong_as_double(((long long)hi << 32) | (unsigned int)lo), a);
   }
 };
 
@@ -368,9 +382,9 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_ker
     if constexpr (!DAG) {
       // chi / b = psi + (c/b) (P+ psi_{s-1} + P- psi_{s+1}), walls included
 #pragma unroll
-      for (int i = 0; i < 12; ++i) v[i] = fmac(cm, sh.m(v[i]), v[i]);
+      for (int i = 0; i < 12; ++i) v[i] = sh.fm(cm, v[i], v[i]);
 #pragma unroll
-      for (int i = 12; i < 24; ++i) v[i] = fmac(cp, sh.p(v[i]), v[i]);
+      for (int i = 12; i < 24; ++i) v[i] = sh.fp(cp, v[i], v[i]);
     }
     T h[12], uh[12], U[18];
     load_link(lks + D * LSTR, U);
@@ -386,9 +400,9 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_ker
     // upper spins come from s+1, lower spins from s-1
     T tmp[24];
 #pragma unroll
-    for (int i = 0; i < 12; ++i) tmp[i] = fmac(cp, sh.p(acc[i]), acc[i]);
+    for (int i = 0; i < 12; ++i) tmp[i] = sh.fp(cp, acc[i], acc[i]);
 #pragma unroll
-    for (int i = 12; i < 24; ++i) tmp[i] = fmac(cm, sh.m(acc[i]), acc[i]);
+    for (int i = 12; i < 24; ++i) tmp[i] = sh.fm(cm, acc[i], acc[i]);
 #pragma unroll
     for (int i = 0; i < 24; ++i) acc[i] = tmp[i];
   }
@@ -403,14 +417,14 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_ker
     for (int i = 0; i < 24; ++i) acc[i] = fmac(al, z[i], hs * acc[i]);
     if constexpr (!DAG) {  // + beta C z
 #pragma unroll
-      for (int i = 0; i < 12; ++i) acc[i] = fmac(bm, sh.m(z[i]), acc[i]);
+      for (int i = 0; i < 12; ++i) acc[i] = sh.fm(bm, z[i], acc[i]);
 #pragma unroll
-      for (int i = 12; i < 24; ++i) acc[i] = fmac(bp, sh.p(z[i]), acc[i]);
+      for (int i = 12; i < 24; ++i) acc[i] = sh.fp(bp, z[i], acc[i]);
     } else {               // + beta C^dag z
 #pragma unroll
-      for (int i = 0; i < 12; ++i) acc[i] = fmac(bp, sh.p(z[i]), acc[i]);
+      for (int i = 0; i < 12; ++i) acc[i] = sh.fp(bp, z[i], acc[i]);
 #pragma unroll
-      for (int i = 12; i < 24; ++i) acc[i] = fmac(bm, sh.m(z[i]), acc[i]);
+      for (int i = 12; i < 24; ++i) acc[i] = sh.fm(bm, z[i], acc[i]);
     }
   } else {
 #pragma unroll
