@@ -139,34 +139,48 @@ int qdwf_create(const qdwf_action* act, int device, qdwf_ctx** out) {
   g.n5h = (long)g.Vh * g.Ls;
 
   // Internal site order of each parity. The lattice is cut into 8 slabs
-  // along z, one per XCD (blocks of consecutive internal sites reach the XCDs
-  // in contiguous ranges); inside a slab, (x, y, z) tiles of tx * ty * tz
-  // sites are swept along t. The sites a XCD works on at any moment then form
-  // a compact 4D region whose neighbours are still in its L2, and all XCDs
-  // advance through t together, so t-neighbours shared across XCDs meet in the
-  // last-level cache. Tile sizes: QDWF_TILE="tx,ty,tz" overrides the default.
+  // along the split dimension, one per XCD (blocks of consecutive internal
+  // sites reach the XCDs in contiguous ranges); inside a slab, tiles over the
+  // other three dimensions are swept along the sweep dimension. The sites a
+  // XCD works on at any moment then form a compact 4D region whose
+  // neighbours are still in its L2, and all XCDs advance along the sweep
+  // together, so neighbours shared across XCDs meet in the last-level cache.
+  // Defaults: split z, sweep t, (x, y, z) tile 32 x 4 x Lz/8. Overrides:
+  // QDWF_ORDER="split,sweep" (dimension numbers 0..3 = x, y, z, t) and
+  // QDWF_TILE="tx,ty,tz[,tt]" (the entry of the sweep dimension is ignored).
   const int* L = g.L;
-  int tile[3] = {std::min(L[0], 16), std::min(L[1], 4), std::max(1, L[2] / 8)};
-  if (const char* e = std::getenv("QDWF_TILE")) {
-    int a = 0, b = 0, cc = 0;
-    if (std::sscanf(e, "%d,%d,%d", &a, &b, &cc) == 3 && a > 0 && b > 0 && cc > 0) {
-      tile[0] = a; tile[1] = b; tile[2] = cc;
+  int sd = 2, wd = 3;
+  if (const char* e = std::getenv("QDWF_ORDER")) {
+    int a = -1, b = -1;
+    if (std::sscanf(e, "%d,%d", &a, &b) == 2 && a >= 0 && a < 4 && b >= 0 && b < 4 && a != b) {
+      sd = a; wd = b;
     }
   }
-  for (int k = 0; k < 3; ++k) c->tile[k] = tile[k];
+  int tile[4] = {std::min(L[0], 32), std::min(L[1], 4), std::max(1, L[2] / 8), 1};
+  if (sd != 2 || wd != 3) {
+    for (int mu = 0; mu < 4; ++mu) tile[mu] = std::min(L[mu], 4);
+    tile[sd] = std::max(1, L[sd] / 8);
+  }
+  if (const char* e = std::getenv("QDWF_TILE")) {
+    int t4[4] = {0, 0, 0, 1};
+    const int n = std::sscanf(e, "%d,%d,%d,%d", &t4[0], &t4[1], &t4[2], &t4[3]);
+    if (n >= 3 && t4[0] > 0 && t4[1] > 0 && t4[2] > 0 && t4[3] > 0)
+      for (int mu = 0; mu < 4; ++mu) tile[mu] = t4[mu];
+  }
+  tile[wd] = 1;
+  for (int k = 0; k < 4; ++k) c->tile[k] = tile[k];
+  c->order[0] = sd;
+  c->order[1] = wd;
   std::vector<int64_t> key(g.V);
   for (int lex = 0; lex < g.V; ++lex) {
     int x[4], r = lex;
     for (int mu = 0; mu < 4; ++mu) { x[mu] = r % L[mu]; r /= L[mu]; }
-    const int zc = (x[2] * 8) / L[2];
-    int64_t k = zc;
-    k = k * L[2] + x[2] / tile[2];
-    k = k * L[1] + x[1] / tile[1];
-    k = k * L[0] + x[0] / tile[0];
-    k = k * L[3] + x[3];
-    k = k * L[2] + x[2] % tile[2];
-    k = k * L[1] + x[1] % tile[1];
-    k = k * L[0] + x[0] % tile[0];
+    int64_t k = (x[sd] * 8) / L[sd];
+    for (int mu = 3; mu >= 0; --mu)
+      if (mu != wd) k = k * L[mu] + x[mu] / tile[mu];
+    k = k * L[wd] + x[wd];
+    for (int mu = 3; mu >= 0; --mu)
+      if (mu != wd) k = k * L[mu] + x[mu] % tile[mu];
     key[lex] = k;
   }
   c->h_site_lex.assign((size_t)2 * g.Vh, 0);

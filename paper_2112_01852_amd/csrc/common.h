@@ -128,7 +128,8 @@ struct qdwf_ctx {
   qdwf::Geom g;
   int32_t* d_nbr;          // [2][8][Vh] neighbour internal index
   int32_t* d_site_lex;     // [2][Vh] lex index of each internal site
-  int tile[3];             // (x, y, z) tile of the traversal order
+  int tile[4];             // tile of the traversal order (1 on the sweep dimension)
+  int order[2];            // split and sweep dimension of the traversal order
   void* d_links[4];        // per precision: [2][4][Vh][18] reals, bc folded in
   bool gauge_set;
   double* d_mat64;         // [MAT_COUNT][2][Ls][Ls]

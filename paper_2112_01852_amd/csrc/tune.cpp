@@ -41,9 +41,9 @@ std::string arch_name(int device) {
 
 std::string cache_key(const qdwf_ctx* c, int prec, int layout, int dagger, int nrhs) {
   char buf[256];
-  snprintf(buf, sizeof(buf), "%dx%dx%dx%d_Ls%d_p%d_l%d_d%d_n%d_t%d.%d.%d_%s", c->g.L[0], c->g.L[1],
-           c->g.L[2], c->g.L[3], c->g.Ls, prec, layout, dagger, nrhs, c->tile[0], c->tile[1],
-           c->tile[2], arch_name(c->device).c_str());
+  snprintf(buf, sizeof(buf), "%dx%dx%dx%d_Ls%d_p%d_l%d_d%d_n%d_t%d.%d.%d.%d_o%d.%d_%s", c->g.L[0],
+           c->g.L[1], c->g.L[2], c->g.L[3], c->g.Ls, prec, layout, dagger, nrhs, c->tile[0],
+           c->tile[1], c->tile[2], c->tile[3], c->order[0], c->order[1], arch_name(c->device).c_str());
   return buf;
 }
 
