@@ -55,6 +55,7 @@ CASES = [
     ((6, 2, 2, 6), 16, MOBIUS),    # Vh = 72 over 16: ragged
     ((4, 2, 4, 6), 12, MOBIUS),    # Ls = 12: 4 idle lanes per wavefront
     ((4, 4, 4, 4), 8, SHAMIR),     # the Shamir FP64 workload shape
+    ((6, 6, 10, 6), 16, MOBIUS),   # partial traversal tiles and uneven XCD slabs; Vh = 1080
 ]
 
 
