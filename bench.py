@@ -9,7 +9,8 @@ HBM. Alongside it: HBM roofline fraction of that kernel (algorithmic bytes),
 the split-plane (RRII) and interleaved (RIRI) layouts side by side, the
 even-odd hop, FP64 / FP16 / BF16 variants, mixed-precision and plain FP64 CG
 solves/s on 24^4 x 16 with smoothed links, and the FP64 CPU oracle timed on
-the host cores on a bounded sample.
+the host cores on the same workload, and the paper's Table 2 domain-wall
+volumes (Shamir D and the even-odd hop, FP64 and FP32).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solver] [--no-cpu]
 """
@@ -126,6 +127,51 @@ def dslash_bench(args, torch, q, I):
         torch.cuda.empty_cache()
     D.close()
     return res, sites
+
+
+# The domain-wall volumes of the paper's Table 2 (x, y, z, t; Ls) and its
+# single-node, one-rank A64FX figures in GFlop/s (DP, SP), quoted as context.
+PAPER_DWF_SHAPES = [((16, 16, 16, 32), 8, (484, 949)), ((16, 16, 16, 32), 16, (477, 958)),
+                    ((24, 24, 24, 48), 8, (476, 960))]
+SHAMIR = dict(M5=1.8, mf=0.01, b=1.0, c=0.0)
+
+
+def paper_shapes_bench(args, torch, q, I):
+    """Shamir domain-wall operator D and the even-odd hop at the paper's
+    Table 2 volumes, FP64 and FP32 storage, RIRI, 1320 flops per 5D site."""
+    out = {}
+    for L, Ls, (dp, sp) in PAPER_DWF_SHAPES:
+        U = I.gauge_field(L, "haar", 2100, dtype=np.complex64)
+        psi = torch.from_numpy(I.gaussian_spinor(L, Ls, 2101, dtype=np.complex64)).cuda()
+        D = q.Dirac(L, Ls, **SHAMIR)
+        D.set_gauge(torch.from_numpy(U))
+        sites = D.V * Ls
+        key = "%dx%dx%dx%dx%d" % (L + (Ls,))
+        row = {}
+        for name, prec, paper in (("f64", q.QDWF_F64, dp), ("f32", q.QDWF_F32, sp)):
+            fin = D.field(prec, q.QDWF_FULL, zero=False)
+            q.qdwf_pack_spinor(D.ctx, fin, prec, q.QDWF_RIRI, psi, q.QDWF_FULL)
+            fout = D.field(prec, q.QDWF_FULL, zero=False)
+            steps = max(args.steps // 2, 5)
+            ms = time_launches(lambda: q.qdwf_apply_D(D.ctx, fout, fin, 0, prec, q.QDWF_RIRI),
+                               steps, 3, torch)
+            half_in, half_out = fin[: fin.numel() // 2], fout[: fout.numel() // 2]
+            ms_eo = time_launches(lambda: q.qdwf_apply_Deo(D.ctx, half_out, half_in, q.QDWF_ODD, 0,
+                                                           prec, q.QDWF_RIRI), steps, 3, torch)
+            pb = fin.element_size()
+            row[name] = {"D_ms": ms, "D_gflops": FLOPS_PER_SITE * sites / (ms * 1e-3) / 1e9,
+                         "D_frac_hbm": algorithmic_bytes_per_site(pb, Ls, False) * sites
+                         / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                         "Deo_ms": ms_eo,
+                         "Deo_gflops": FLOPS_PER_SITE * sites / 2 / (ms_eo * 1e-3) / 1e9,
+                         "paper_a64fx_gflops": paper}
+            del fin, fout
+        out[key] = row
+        log("paper shape", key, row)
+        D.close()
+        del psi
+        torch.cuda.empty_cache()
+    return out
 
 
 def copy_probe(torch, nbytes=2 << 30, steps=20):
@@ -306,6 +352,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-paper", action="store_true",
+                    help="skip the Table 2 volumes")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-load", type=float, default=0.9,
                     help="offered load relative to one-at-a-time plain FP64 service")
@@ -328,6 +376,7 @@ def main():
     best = min(cands, key=lambda k: dres[k]["ms"])
     best_layout = best.split("_")[-1]
     head = dres[best]
+    paper = None if args.no_paper else paper_shapes_bench(args, torch, q, I)
     solver = None if args.no_solver else solver_bench(args, torch, q, I)
     multi = None if args.no_multi else multi_rhs_bench(args, torch, q, I)
     served = None if args.no_serve else serving_bench(args, torch, q)
@@ -358,6 +407,7 @@ def main():
                      "algorithmic_bytes": algorithmic_bytes_per_site(4, 16, False) * sites},
         "attainable_hbm": probe,
         "dslash": dres,
+        "paper_dwf_shapes": paper,
         "solver_24x24x24x24x16": solver,
         "multi_rhs_16x16x16x16x16_n24": multi,
         "serving": served,
