@@ -10,7 +10,8 @@ the split-plane (RRII) and interleaved (RIRI) layouts side by side, the
 even-odd hop, FP64 / FP16 / BF16 variants, mixed-precision and plain FP64 CG
 solves/s on 24^4 x 16 with smoothed links, and the FP64 CPU oracle timed on
 the host cores on the same workload, and the paper's Table 2 domain-wall
-volumes (Shamir D and the even-odd hop, FP64 and FP32).
+volumes (Shamir D and the even-odd hop, FP64 and FP32) and the Wilson Dslash
+kernel at its Table 1 volumes.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solver] [--no-cpu]
 """
@@ -168,6 +169,51 @@ def paper_shapes_bench(args, torch, q, I):
             del fin, fout
         out[key] = row
         log("paper shape", key, row)
+        D.close()
+        del psi
+        torch.cuda.empty_cache()
+    return out
+
+
+# The Wilson Dslash volumes of the paper's Table 1 and its single-node,
+# one-rank A64FX figures in GFlop/s (DP, SP), quoted as context.
+PAPER_WILSON_SHAPES = [((16, 16, 16, 32), (360, 893)), ((24, 24, 24, 48), (350, 990)),
+                       ((32, 32, 32, 64), (339, 1023))]
+
+
+def wilson_shapes_bench(args, torch, q, I):
+    """The Wilson Dslash kernel D_h (4D fields, Ls = 1) at the paper's Table 1
+    volumes, both parities in one launch and one parity, FP64 and FP32,
+    RIRI, 1320 flops per site; algorithmic bytes per site: spinor in and out
+    plus the 4 links of the site (72 reals), 144 link reals for one parity."""
+    out = {}
+    for L, (dp, sp) in PAPER_WILSON_SHAPES:
+        U = I.gauge_field(L, "haar", 2200, dtype=np.complex64)
+        psi = torch.from_numpy(I.gaussian_spinor(L, 1, 2201, dtype=np.complex64)).cuda()
+        D = q.Dirac(L, 1, **SHAMIR)
+        D.set_gauge(torch.from_numpy(U))
+        key = "%dx%dx%dx%d" % L
+        row = {}
+        for name, prec, paper in (("f64", q.QDWF_F64, dp), ("f32", q.QDWF_F32, sp)):
+            fin = D.field(prec, q.QDWF_FULL, zero=False)
+            q.qdwf_pack_spinor(D.ctx, fin, prec, q.QDWF_RIRI, psi, q.QDWF_FULL)
+            fout = D.field(prec, q.QDWF_FULL, zero=False)
+            steps = max(args.steps // 2, 5)
+            ms = time_launches(lambda: q.qdwf_apply_Dh(D.ctx, fout, fin, q.QDWF_FULL, 0, prec,
+                                                       q.QDWF_RIRI), steps, 3, torch)
+            half_in, half_out = fin[: fin.numel() // 2], fout[: fout.numel() // 2]
+            ms_eo = time_launches(lambda: q.qdwf_apply_Dh(D.ctx, half_out, half_in, q.QDWF_ODD, 0,
+                                                          prec, q.QDWF_RIRI), steps, 3, torch)
+            pb = fin.element_size()
+            gbs = (24 + 24 + 72) * pb * D.V / (ms * 1e-3) / 1e9
+            row[name] = {"Dh_ms": ms, "Dh_gflops": FLOPS_PER_SITE * D.V / (ms * 1e-3) / 1e9,
+                         "Dh_frac_hbm": gbs / HBM_PEAK_GBS,
+                         "Dh_eo_ms": ms_eo,
+                         "Dh_eo_gflops": FLOPS_PER_SITE * D.V / 2 / (ms_eo * 1e-3) / 1e9,
+                         "paper_a64fx_gflops": paper}
+            del fin, fout
+        out[key] = row
+        log("wilson shape", key, row)
         D.close()
         del psi
         torch.cuda.empty_cache()
@@ -353,7 +399,7 @@ def main():
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-paper", action="store_true",
-                    help="skip the Table 2 volumes")
+                    help="skip the Table 1 and Table 2 volumes")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-load", type=float, default=0.9,
                     help="offered load relative to one-at-a-time plain FP64 service")
@@ -377,6 +423,7 @@ def main():
     best_layout = best.split("_")[-1]
     head = dres[best]
     paper = None if args.no_paper else paper_shapes_bench(args, torch, q, I)
+    wilson = None if args.no_paper else wilson_shapes_bench(args, torch, q, I)
     solver = None if args.no_solver else solver_bench(args, torch, q, I)
     multi = None if args.no_multi else multi_rhs_bench(args, torch, q, I)
     served = None if args.no_serve else serving_bench(args, torch, q)
@@ -408,6 +455,7 @@ def main():
         "attainable_hbm": probe,
         "dslash": dres,
         "paper_dwf_shapes": paper,
+        "paper_wilson_shapes": wilson,
         "solver_24x24x24x24x16": solver,
         "multi_rhs_16x16x16x16x16_n24": multi,
         "serving": served,

@@ -21,7 +21,8 @@
  *   hop         (D_h psi)(x,s) = sum_mu [ (1-g_mu) U_mu(x) psi(x+mu,s)
  *                                       + (1+g_mu) U_mu(x-mu)^dag psi(x-mu,s) ],
  *               each hop across the mu boundary multiplied by bc[mu].
- *   Wilson      D_W = (4 - M5) - D_h / 2.
+ *   Wilson      D_W = (4 - M5) - D_h / 2 inside D; the standalone Wilson
+ *               operator of qdwf_apply_Dw is (4 + m) - D_h / 2 for a mass m.
  *   5th dim     (S_u psi)_s = psi_{s+1}, row Ls-1 takes -mf psi_0;
  *               (S_d psi)_s = psi_{s-1}, row 0 takes -mf psi_{Ls-1};
  *               C = P- S_u + P+ S_d; A = b + c C; B = 1 - C.
@@ -36,15 +37,16 @@
  *   gauge   U[mu][t][z][y][x][a][b]                 (mu = x, y, z, t)
  *   spinor  psi[rhs][s][t][z][y][x][spin][colour]
  * Internal spinor fields (what the operators take) are produced by
- * qdwf_pack_spinor. A half field holds one parity: (V/2)*Ls 5D sites, site
- * index j = i*Ls + s, 24 reals per site, where i numbers the 4D sites of that
- * parity in the library's traversal order (8 slabs along z, one per XCD, each
- * in (t, z, y, x) order; qdwf_geometry_tables exports it). A full field is the even half
- * followed by the odd half. nrhs fields of the same kind are stored back to
- * back. Two layouts of the 24 reals of a site exist (Section 4.3 compares the
- * same two choices for SVE registers):
- *   QDWF_RIRI  interleaved complex: field[j][spin][colour][re,im]
- *   QDWF_RRII  split planes:        field[re/im][spin][colour][j] per parity half
+ * qdwf_pack_spinor. A half field holds one parity: (V/2)*Ls 5D sites (i, s),
+ * 24 reals per site, where i numbers the 4D sites of that parity in the
+ * library's traversal order (8 slabs along z, one per XCD, (x,y,z) tiles
+ * swept along t; qdwf_geometry_tables exports it). A full field is the even
+ * half followed by the odd half. nrhs fields of the same kind are stored
+ * back to back. Two layouts of the 24 reals c = (spin*3 + colour)*2 + re/im
+ * exist (Section 4.3 compares the same two choices for SVE registers):
+ *   QDWF_RIRI  interleaved complex, blocked over the slices of a 4D site in
+ *              chunks of 4 reals: offset i*Ls*24 + (c/4)*Ls*4 + s*4 + c%4
+ *   QDWF_RRII  split planes: offset ((c%2)*12 + c/2)*(V/2)*Ls + i*Ls + s
  * Precisions give the storage type of a real; arithmetic is FP64 for QDWF_F64
  * and FP32 for the others (FP16/BF16 are storage only, rounded to nearest even).
  */
@@ -98,7 +100,7 @@ extern "C" {
 /* ---- types ------------------------------------------------------------ */
 typedef struct {
   int32_t L[4];     /* extents x, y, z, t; each even and >= 2                 */
-  int32_t Ls;       /* fifth-dimension extent, 2 <= Ls <= 64                  */
+  int32_t Ls;       /* fifth-dimension extent, 1 <= Ls <= 64 (1: 4D fields)    */
   int32_t bc[4];    /* +1 periodic, -1 antiperiodic per direction            */
   double M5;        /* domain-wall height                                    */
   double mf;        /* quark mass (wall coupling -mf)                        */
@@ -169,6 +171,21 @@ int qdwf_unpack_spinor(qdwf_ctx* ctx, void* dst, int dst_prec, const void* src, 
  * (dagger = 1). in, out: full fields, nrhs right-hand sides. */
 int qdwf_apply_D(qdwf_ctx* ctx, void* out, const void* in, int dagger, int prec, int layout,
                  int nrhs, void* stream);
+
+/* Wilson Dslash kernel (Section 4.1, Table 1): out = D_h in, or D_h^dag in
+ * (dagger = 1, the projectors (1 -+ g_mu) swapped), on every slice s. With
+ * subset = QDWF_FULL, in and out are full fields; with subset = QDWF_EVEN or
+ * QDWF_ODD, out is the half field of that parity and in the half field of
+ * the other parity. For Ls = 1 these are 4D Wilson fields. Links and the
+ * boundary factors bc are those of the context; M5, mf, b, c are not used.
+ * 1320 flops per output site. */
+int qdwf_apply_Dh(qdwf_ctx* ctx, void* out, const void* in, int subset, int dagger, int prec,
+                  int layout, int nrhs, void* stream);
+
+/* Wilson operator: out = (4 + mass) in - 1/2 D_h in (dagger = 1: with
+ * D_h^dag) on full fields, every slice s. mass must be finite. */
+int qdwf_apply_Dw(qdwf_ctx* ctx, void* out, const void* in, double mass, int dagger, int prec,
+                  int layout, int nrhs, void* stream);
 
 /* 4D-local block on `subset` fields: which = QDWF_MEE_FWD gives M_ee,
  * QDWF_MEE_INV gives M_ee^-1; dagger = 1 gives the adjoint. M_ee = M_oo, so

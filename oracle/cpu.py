@@ -120,6 +120,13 @@ def hop(a: Action, U, psi, dagger: bool = False) -> np.ndarray:
     return out
 
 
+def wilson(a: Action, U, psi, mass: float, dagger: bool = False) -> np.ndarray:
+    """Wilson operator (4 + mass) psi - D_h psi / 2 on every slice s, or with
+    D_h^dag: the standalone Wilson Dslash operator (Section 4.1, Table 1).
+    Only a.L and a.bc are used."""
+    return (4.0 + float(mass)) * _c128(psi) - 0.5 * hop(a, U, psi, dagger)
+
+
 def dwf(a: Action, U, psi, dagger: bool = False) -> np.ndarray:
     """Mobius domain-wall operator D psi = D_W A psi + B psi (or D^dag psi)."""
     U, psi = _c128(U), _c128(psi)

@@ -113,7 +113,7 @@ int qdwf_create(const qdwf_action* act, int device, qdwf_ctx** out) {
     if (act->bc[mu] != 1 && act->bc[mu] != -1)
       return fail(QDWF_EINVAL, "bc[%d] = %d must be +1 or -1", mu, act->bc[mu]);
   }
-  if (act->Ls < 2 || act->Ls > 64) return fail(QDWF_EINVAL, "Ls = %d must be in [2, 64]", act->Ls);
+  if (act->Ls < 1 || act->Ls > 64) return fail(QDWF_EINVAL, "Ls = %d must be in [1, 64]", act->Ls);
   const double V = (double)act->L[0] * act->L[1] * act->L[2] * act->L[3];
   if (V * act->Ls / 2 * 24 > 9.0e18 || V > 2.0e9) return fail(QDWF_EINVAL, "lattice too large");
   if (!(std::fabs(act->b) > 0.0) || !std::isfinite(act->b))
@@ -351,6 +351,66 @@ int qdwf_apply_D(qdwf_ctx* ctx, void* out, const void* in, int dagger, int prec,
   a.alpha = alpha_of(ctx);
   a.beta = beta_of(ctx);
   return launch_hop(ctx, prec, layout, dagger ? 1 : 0, a, S(stream));
+}
+
+int qdwf_apply_Dh(qdwf_ctx* ctx, void* out, const void* in, int subset, int dagger, int prec,
+                  int layout, int nrhs, void* stream) {
+  TRY(common_checks(ctx, out, in, prec, layout, nrhs));
+  if (subset != QDWF_EVEN && subset != QDWF_ODD && subset != QDWF_FULL)
+    return fail(QDWF_EINVAL, "subset must be 0, 1 or 2");
+  if (out == in) return fail(QDWF_EINVAL, "out must not alias in");
+  DeviceGuard dg(ctx->device);
+  const long half = ctx->g.n5h * 24;
+  const size_t bytes = prec_bytes(prec);
+  const char* ib = reinterpret_cast<const char*>(in);
+  char* ob = reinterpret_cast<char*>(out);
+  HopArgs a = {};
+  if (subset == QDWF_FULL) {
+    a.in[0] = ib + half * bytes;   // output even reads odd input
+    a.in[1] = ib;
+    a.out[0] = ob;
+    a.out[1] = ob + half * bytes;
+    a.rs_in = a.rs_out = 2 * half;
+    a.par0 = 0;
+    a.npar = 2;
+  } else {
+    a.in[subset] = ib;             // half field of the other parity
+    a.out[subset] = ob;
+    a.rs_in = a.rs_out = half;
+    a.par0 = subset;
+    a.npar = 1;
+  }
+  a.nrhs = nrhs;
+  a.epi = 0;
+  a.hop_scale = 1.0;
+  return launch_wilson(ctx, prec, layout, dagger ? 1 : 0, a, S(stream));
+}
+
+int qdwf_apply_Dw(qdwf_ctx* ctx, void* out, const void* in, double mass, int dagger, int prec,
+                  int layout, int nrhs, void* stream) {
+  TRY(common_checks(ctx, out, in, prec, layout, nrhs));
+  if (!std::isfinite(mass)) return fail(QDWF_EINVAL, "mass must be finite");
+  if (out == in) return fail(QDWF_EINVAL, "out must not alias in");
+  DeviceGuard dg(ctx->device);
+  const long half = ctx->g.n5h * 24;
+  const size_t bytes = prec_bytes(prec);
+  const char* ib = reinterpret_cast<const char*>(in);
+  char* ob = reinterpret_cast<char*>(out);
+  HopArgs a = {};
+  a.in[0] = ib + half * bytes;
+  a.in[1] = ib;
+  a.out[0] = ob;
+  a.out[1] = ob + half * bytes;
+  a.z[0] = ib;
+  a.z[1] = ib + half * bytes;
+  a.rs_in = a.rs_out = a.rs_z = 2 * half;
+  a.par0 = 0;
+  a.npar = 2;
+  a.nrhs = nrhs;
+  a.epi = 1;
+  a.hop_scale = -0.5;
+  a.alpha = 4.0 + mass;
+  return launch_wilson(ctx, prec, layout, dagger ? 1 : 0, a, S(stream));
 }
 
 int qdwf_apply_Mee(qdwf_ctx* ctx, void* out, const void* in, int subset, int dagger, int which,

@@ -164,6 +164,12 @@ struct HopArgs {
 int launch_hop(qdwf_ctx* ctx, int prec, int layout, int dagger, const HopArgs& a,
                hipStream_t st, const HopShape* shape = nullptr);
 
+// Wilson family (no fifth-dimension terms, links read from global memory):
+// out = hop_scale * D_h in  (+ alpha z when epi), D_h^dag when dagger, with
+// the same argument conventions as launch_hop (beta is unused).
+int launch_wilson(qdwf_ctx* ctx, int prec, int layout, int dagger, const HopArgs& a,
+                  hipStream_t st);
+
 // out = K in with K the chiral Ls x Ls matrices of `kind`, on `nhalf` half
 // fields of nrhs right-hand sides each (half fields are consecutive with
 // stride rs_half reals inside one rhs block of stride rs reals).

@@ -76,6 +76,8 @@ _SIG = {
     "qdwf_apply_D": ([_P, _P, _P, _I, _I, _I, _I, _P], _I),
     "qdwf_apply_Mee": ([_P, _P, _P, _I, _I, _I, _I, _I, _I, _P], _I),
     "qdwf_apply_Deo": ([_P, _P, _P, _I, _I, _I, _I, _I, _P], _I),
+    "qdwf_apply_Dh": ([_P, _P, _P, _I, _I, _I, _I, _I, _P], _I),
+    "qdwf_apply_Dw": ([_P, _P, _P, ctypes.c_double, _I, _I, _I, _I, _P], _I),
     "qdwf_apply_Mpc": ([_P, _P, _P, _I, _I, _I, _I, _P, _P], _I),
     "qdwf_apply_MdagM": ([_P, _P, _P, _I, _I, _I, _P, _P], _I),
     "qdwf_workspace_bytes": ([_P, _I, _I, _I], ctypes.c_size_t),
@@ -214,6 +216,16 @@ def qdwf_apply_Mee(ctx, out, inp, subset, dagger, which, prec, layout, nrhs=1, s
 def qdwf_apply_Deo(ctx, out, inp, out_parity, dagger, prec, layout, nrhs=1, stream=None):
     _check(lib().qdwf_apply_Deo(ctx, _ptr(out, "out"), _ptr(inp, "in"), int(out_parity),
                                 int(dagger), int(prec), int(layout), int(nrhs), _stream(stream)))
+
+
+def qdwf_apply_Dh(ctx, out, inp, subset, dagger, prec, layout, nrhs=1, stream=None):
+    _check(lib().qdwf_apply_Dh(ctx, _ptr(out, "out"), _ptr(inp, "in"), int(subset), int(dagger),
+                               int(prec), int(layout), int(nrhs), _stream(stream)))
+
+
+def qdwf_apply_Dw(ctx, out, inp, mass, dagger, prec, layout, nrhs=1, stream=None):
+    _check(lib().qdwf_apply_Dw(ctx, _ptr(out, "out"), _ptr(inp, "in"), float(mass), int(dagger),
+                               int(prec), int(layout), int(nrhs), _stream(stream)))
 
 
 def qdwf_workspace_bytes(ctx, op, prec, nrhs=1) -> int:

@@ -239,5 +239,7 @@ def test_invalid_arguments_raise_before_launch(q):
     with pytest.raises(q.QdwfError):
         q.qdwf_create(q.make_action((3, 4, 4, 4), 8))   # odd extent
     with pytest.raises(q.QdwfError):
-        q.qdwf_create(q.make_action((4, 4, 4, 4), 1))   # Ls
+        q.qdwf_create(q.make_action((4, 4, 4, 4), 0))   # Ls below 1
+    with pytest.raises(q.QdwfError):
+        q.qdwf_create(q.make_action((4, 4, 4, 4), 65))  # Ls above 64
     D.close()

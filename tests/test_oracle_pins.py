@@ -9,6 +9,7 @@ domain-wall operator's effective 4D operator.
 import dataclasses
 
 import numpy as np
+import scipy.sparse as sp
 import pytest
 
 from oracle import cpu, dense, freefield
@@ -122,6 +123,46 @@ def test_free_field_wilson_plane_wave(oracle_lib, n):
     K = sum(2 * np.cos(p[mu]) * np.eye(4) - 2j * np.sin(p[mu]) * g[mu] for mu in range(4))
     expect = freefield.plane_wave(a.L, a.Ls, p, np.einsum("ab,sbc->sac", K, u))
     assert _rel(cpu.hop(a, U, pw), expect) < 1e-14
+
+
+@pytest.mark.parametrize("n", [(1, 2, 3, 0), (0, 3, 1, 2)])
+def test_free_field_wilson_plane_wave_4d(oracle_lib, n):
+    """Ls = 1 (4D Wilson fields): D_W(m) on exp(ip.x)u is
+    exp(ip.x) [(4 + m - sum_mu cos p) + i sum_mu g sin p] u."""
+    a = cpu.Action(L=(4, 6, 4, 4), Ls=1, **SHAMIR)
+    U = I.gauge_field(a.L, "unit", 0)
+    p = freefield.momenta(a.L, a.bc, n)
+    g, _ = dense.gamma_matrices()
+    u = I.gaussian_spinor((1, 1, 1, 1), 1, 22).reshape(1, 4, 3)
+    pw = freefield.plane_wave(a.L, 1, p, u)
+    m = 0.37
+    K = (4 + m - sum(np.cos(p))) * np.eye(4) + 1j * sum(np.sin(p[mu]) * g[mu] for mu in range(4))
+    expect = freefield.plane_wave(a.L, 1, p, np.einsum("ab,sbc->sac", K, u))
+    assert _rel(cpu.wilson(a, U, pw, m), expect) < 1e-14
+
+
+def test_wilson_matches_sparse_matrix(oracle_lib):
+    """The 4D Wilson operator and its adjoint equal (4 + m) - D_h/2 built as a
+    sparse Kronecker matrix (adjoint = conjugate transpose)."""
+    a = cpu.Action(L=(4, 2, 2, 4), Ls=1, **SHAMIR)
+    U = I.gauge_field(a.L, "haar", 61)
+    psi = I.gaussian_spinor(a.L, 1, 62)
+    m = -0.25
+    W = (4 + m) * sp.identity(a.V * 12) - 0.5 * dense.hop_matrix(a.L, U, a.bc)
+    for dag in (False, True):
+        M = W.conj().T if dag else W
+        expect = (M @ psi.ravel()).reshape(psi.shape)
+        assert _rel(cpu.wilson(a, U, psi, m, dagger=dag), expect) < 1e-14
+
+
+def test_wilson_gamma5_hermiticity(oracle_lib):
+    """g5 D_W g5 = D_W^dag (an exact symmetry, on Haar links)."""
+    a = cpu.Action(L=(4, 4, 2, 2), Ls=1, **SHAMIR)
+    U = I.gauge_field(a.L, "haar", 63)
+    psi = I.gaussian_spinor(a.L, 1, 64)
+    g5 = lambda x: np.concatenate([x[..., :2, :], -x[..., 2:, :]], axis=-2)
+    lhs = g5(cpu.wilson(a, U, g5(psi), 0.1))
+    assert _rel(lhs, cpu.wilson(a, U, psi, 0.1, dagger=True)) < 1e-14
 
 
 @pytest.mark.parametrize("params", [SHAMIR, MOBIUS])
