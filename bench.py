@@ -11,7 +11,8 @@ even-odd hop, FP64 / FP16 / BF16 variants, mixed-precision and plain FP64 CG
 solves/s on 24^4 x 16 with smoothed links, and the FP64 CPU oracle timed on
 the host cores on the same workload, and the paper's Table 2 domain-wall
 volumes (Shamir D and the even-odd hop, FP64 and FP32) and the Wilson Dslash
-kernel at its Table 1 volumes.
+kernel at its Table 1 volumes, and the per-site SU(3) product and triad
+streaming probes.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solver] [--no-cpu]
 """
@@ -220,6 +221,40 @@ def wilson_shapes_bench(args, torch, q, I):
     return out
 
 
+def streaming_bench(args, torch, q, I):
+    """Per-site SU(3) product (C = A B on a 4D volume of 3x3 complex matrices,
+    198 flops and 3 x 18 reals per site) over a sweep of volumes, as in the
+    paper's Benchmark_su3 study, and the STREAM triad on 2^28 reals."""
+    out = {"su3": {}, "triad": {}}
+    for L in (8, 16, 24, 32, 48):
+        n = L ** 4
+        row = {}
+        for name, prec, dt in (("f64", q.QDWF_F64, torch.float64), ("f32", q.QDWF_F32, torch.float32)):
+            A = torch.randn(n * 18, dtype=dt, device="cuda")
+            B = torch.randn(n * 18, dtype=dt, device="cuda")
+            C = torch.empty_like(A)
+            steps = max(args.steps // 2, 5)
+            ms = time_launches(lambda: q.qdwf_su3_mul(C, A, B, n, prec), steps, 3, torch)
+            gbs = 54 * A.element_size() * n / (ms * 1e-3) / 1e9
+            row[name] = {"ms": ms, "GBs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
+                         "gflops": 198 * n / (ms * 1e-3) / 1e9}
+            del A, B, C
+        out["su3"][f"{L}^4"] = row
+        log("su3", L, row)
+    n = 1 << 28
+    for name, prec, dt in (("f64", q.QDWF_F64, torch.float64), ("f32", q.QDWF_F32, torch.float32)):
+        b = torch.randn(n, dtype=dt, device="cuda")
+        c = torch.randn(n, dtype=dt, device="cuda")
+        a = torch.empty_like(b)
+        ms = time_launches(lambda: q.qdwf_triad(a, b, c, 0.5, n, prec), max(args.steps // 2, 5), 3, torch)
+        gbs = 3 * b.element_size() * n / (ms * 1e-3) / 1e9
+        out["triad"][name] = {"n": n, "ms": ms, "GBs": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
+        del a, b, c
+    log("triad", out["triad"])
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_probe(torch, nbytes=2 << 30, steps=20):
     """Attainable HBM bandwidth: a plain device-to-device copy of 2 GiB
     (read + write counted), timed with HIP events."""
@@ -399,7 +434,7 @@ def main():
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-paper", action="store_true",
-                    help="skip the Table 1 and Table 2 volumes")
+                    help="skip the Table 1 / Table 2 volumes and the streaming probes")
     ap.add_argument("--serve-requests", type=int, default=24)
     ap.add_argument("--serve-load", type=float, default=0.9,
                     help="offered load relative to one-at-a-time plain FP64 service")
@@ -424,6 +459,7 @@ def main():
     head = dres[best]
     paper = None if args.no_paper else paper_shapes_bench(args, torch, q, I)
     wilson = None if args.no_paper else wilson_shapes_bench(args, torch, q, I)
+    streaming = None if args.no_paper else streaming_bench(args, torch, q, I)
     solver = None if args.no_solver else solver_bench(args, torch, q, I)
     multi = None if args.no_multi else multi_rhs_bench(args, torch, q, I)
     served = None if args.no_serve else serving_bench(args, torch, q)
@@ -456,6 +492,7 @@ def main():
         "dslash": dres,
         "paper_dwf_shapes": paper,
         "paper_wilson_shapes": wilson,
+        "streaming_probes": streaming,
         "solver_24x24x24x24x16": solver,
         "multi_rhs_16x16x16x16x16_n24": multi,
         "serving": served,

@@ -212,6 +212,20 @@ int qdwf_apply_MdagM(qdwf_ctx* ctx, void* out, const void* in, int prec, int lay
 /* Device workspace size in bytes for an operation (see QDWF_OP_*). */
 size_t qdwf_workspace_bytes(const qdwf_ctx* ctx, int op, int prec, int nrhs);
 
+/* ---- streaming probes (no context) ------------------------------------- */
+/* Per-site SU(3) product of the Benchmark_su3 study (Section 4.2):
+ * C[i] = A[i] B[i] for i < n, each a 3x3 complex matrix stored row-major with
+ * interleaved complex (18 reals), FP64 or FP32 (prec). Device arrays on
+ * `device`, C must not alias A or B; n = 0 launches nothing. 198 real flops
+ * and 54 reals of traffic per matrix. Asynchronous on `stream`. */
+int qdwf_su3_mul(void* C, const void* A, const void* B, int64_t n, int prec, int device,
+                 void* stream);
+
+/* STREAM triad (Section 3): a[i] = b[i] + s c[i] for i < n reals, FP64 or
+ * FP32. a may equal b or c element for element; s must be finite. */
+int qdwf_triad(void* a, const void* b, const void* c, double s, int64_t n, int prec, int device,
+               void* stream);
+
 /* ---- reductions ------------------------------------------------------- */
 /* Per right-hand side r: out[2r] = Re <x_r, y_r>, out[2r+1] = Im <x_r, y_r>,
  * accumulated in FP64 with a fixed reduction order (bitwise reproducible for

@@ -9,4 +9,5 @@ code with the HIP path; only the seeded input generators are common to both.
                           operators from Kronecker products, for small lattices.
 * ``oracle.geometry``  -- checkerboard and neighbour tables by enumeration.
 * ``oracle.freefield`` -- unit-link closed forms in momentum space.
+* ``oracle.streaming`` -- per-site SU(3) product and triad of the memory probes.
 """

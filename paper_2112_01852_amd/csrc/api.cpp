@@ -413,6 +413,34 @@ int qdwf_apply_Dw(qdwf_ctx* ctx, void* out, const void* in, double mass, int dag
   return launch_wilson(ctx, prec, layout, dagger ? 1 : 0, a, S(stream));
 }
 
+int qdwf_su3_mul(void* C, const void* A, const void* B, int64_t n, int prec, int device,
+                 void* stream) {
+  if (n < 0) return fail(QDWF_EINVAL, "n must be >= 0");
+  if (prec != QDWF_F64 && prec != QDWF_F32) return fail(QDWF_EINVAL, "precision must be F64 or F32");
+  if (n > 0) {
+    TRY(check_ptr(C, "C"));
+    TRY(check_ptr(A, "A"));
+    TRY(check_ptr(B, "B"));
+    if (C == A || C == B) return fail(QDWF_EINVAL, "C must not alias A or B");
+  }
+  DeviceGuard dg(device);
+  return launch_su3_mul(C, A, B, (long)n, prec, S(stream));
+}
+
+int qdwf_triad(void* a, const void* b, const void* c, double s, int64_t n, int prec, int device,
+               void* stream) {
+  if (n < 0) return fail(QDWF_EINVAL, "n must be >= 0");
+  if (prec != QDWF_F64 && prec != QDWF_F32) return fail(QDWF_EINVAL, "precision must be F64 or F32");
+  if (!std::isfinite(s)) return fail(QDWF_EINVAL, "s must be finite");
+  if (n > 0) {
+    TRY(check_ptr(a, "a"));
+    TRY(check_ptr(b, "b"));
+    TRY(check_ptr(c, "c"));
+  }
+  DeviceGuard dg(device);
+  return launch_triad(a, b, c, s, (long)n, prec, S(stream));
+}
+
 int qdwf_apply_Mee(qdwf_ctx* ctx, void* out, const void* in, int subset, int dagger, int which,
                    int prec, int layout, int nrhs, void* stream) {
   CTX_CHECK(ctx);

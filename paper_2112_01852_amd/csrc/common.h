@@ -170,6 +170,12 @@ int launch_hop(qdwf_ctx* ctx, int prec, int layout, int dagger, const HopArgs& a
 int launch_wilson(qdwf_ctx* ctx, int prec, int layout, int dagger, const HopArgs& a,
                   hipStream_t st);
 
+// Streaming probes: C[i] = A[i] B[i] for n 3x3 complex matrices, and
+// a = b + s c for n reals (FP64 or FP32).
+int launch_su3_mul(void* C, const void* A, const void* B, long n, int prec, hipStream_t st);
+int launch_triad(void* a, const void* b, const void* c, double s, long n, int prec,
+                 hipStream_t st);
+
 // out = K in with K the chiral Ls x Ls matrices of `kind`, on `nhalf` half
 // fields of nrhs right-hand sides each (half fields are consecutive with
 // stride rs_half reals inside one rhs block of stride rs reals).

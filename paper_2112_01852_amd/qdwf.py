@@ -76,6 +76,8 @@ _SIG = {
     "qdwf_apply_D": ([_P, _P, _P, _I, _I, _I, _I, _P], _I),
     "qdwf_apply_Mee": ([_P, _P, _P, _I, _I, _I, _I, _I, _I, _P], _I),
     "qdwf_apply_Deo": ([_P, _P, _P, _I, _I, _I, _I, _I, _P], _I),
+    "qdwf_su3_mul": ([_P, _P, _P, ctypes.c_int64, _I, _I, _P], _I),
+    "qdwf_triad": ([_P, _P, _P, ctypes.c_double, ctypes.c_int64, _I, _I, _P], _I),
     "qdwf_apply_Dh": ([_P, _P, _P, _I, _I, _I, _I, _I, _P], _I),
     "qdwf_apply_Dw": ([_P, _P, _P, ctypes.c_double, _I, _I, _I, _I, _P], _I),
     "qdwf_apply_Mpc": ([_P, _P, _P, _I, _I, _I, _I, _P, _P], _I),
@@ -226,6 +228,16 @@ def qdwf_apply_Dh(ctx, out, inp, subset, dagger, prec, layout, nrhs=1, stream=No
 def qdwf_apply_Dw(ctx, out, inp, mass, dagger, prec, layout, nrhs=1, stream=None):
     _check(lib().qdwf_apply_Dw(ctx, _ptr(out, "out"), _ptr(inp, "in"), float(mass), int(dagger),
                                int(prec), int(layout), int(nrhs), _stream(stream)))
+
+
+def qdwf_su3_mul(C, A, B, n, prec, device=0, stream=None):
+    _check(lib().qdwf_su3_mul(_ptr(C, "C"), _ptr(A, "A"), _ptr(B, "B"), int(n), int(prec),
+                              int(device), _stream(stream)))
+
+
+def qdwf_triad(a, b, c, s, n, prec, device=0, stream=None):
+    _check(lib().qdwf_triad(_ptr(a, "a"), _ptr(b, "b"), _ptr(c, "c"), float(s), int(n), int(prec),
+                            int(device), _stream(stream)))
 
 
 def qdwf_workspace_bytes(ctx, op, prec, nrhs=1) -> int:

@@ -398,3 +398,32 @@ def test_sampled_sites_match_full_field(oracle_lib, dagger):
     idx = np.random.default_rng(3).choice(a.Ls * a.V, 64, replace=False)
     idx = np.concatenate([idx, [0, a.V - 1, (a.Ls - 1) * a.V, a.Ls * a.V - 1]])
     assert np.abs(cpu.dwf_sites(a, U, psi, idx, dagger=dagger) - full[idx]).max() < 1e-13
+
+
+# ------------------------------------------------------- streaming probes
+def test_su3_product_pins():
+    """Brute-force triple loop on a few matrices; SU(3) closure (unitary,
+    det 1); the identity is neutral; the product is not commutative."""
+    from oracle import streaming
+    A = I.haar_su3(6, 81)
+    B = I.haar_su3(6, 82)
+    C = streaming.su3_mul(A, B)
+    for n in range(6):
+        for i in range(3):
+            for k in range(3):
+                ref = sum(A[n, i, j] * B[n, j, k] for j in range(3))
+                assert abs(C[n, i, k] - ref) < 1e-15
+    eye = np.broadcast_to(np.eye(3), A.shape)
+    assert np.allclose(np.conj(np.swapaxes(C, 1, 2)) @ C, eye, atol=1e-14)
+    assert np.allclose(np.linalg.det(C), 1.0, atol=1e-14)
+    assert np.array_equal(streaming.su3_mul(eye, B), B)
+    assert np.abs(streaming.su3_mul(B, A) - C).max() > 1e-3
+    assert streaming.FLOPS_PER_SU3_MUL == 27 * 6 + 18 * 2
+
+
+def test_triad_pins():
+    from oracle import streaming
+    b = np.arange(7, dtype=np.float64)
+    c = np.full(7, 0.5)
+    assert np.array_equal(streaming.triad(b, c, 2.0), b + 1.0)
+    assert np.array_equal(streaming.triad(b, c, 0.0), b)
