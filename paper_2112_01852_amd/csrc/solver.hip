@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <initializer_list>
 
 #include "common.h"
 #include "solver.h"
@@ -47,16 +48,82 @@ template <class S> __device__ inline double rd(const S* p, long i) {
   return (double)Store<S>::to(p[i]);
 }
 
-// part[r*NB + blk] = sum over this block's share of a_r . b_r (all reals)
+// Work split of the vectorised BLAS kernels: block b takes a contiguous range
+// of tiles of 512 reals (one stream per block through memory), its wavefronts
+// taking the tiles in turn, and in tile t lane l owns the reals
+// t*512 + j*64*E + l*E + e (j < 8/E, e < E), E = 16 bytes over the widest
+// storage type of the kernel's fields. Every load or store of E reals is then
+// one piece of a contiguous run across the wavefront.
+constexpr int TILE = 512;
+
+template <int BYTES> struct Word;
+template <> struct Word<16> { typedef uint4 t; };
+template <> struct Word<8> { typedef uint2 t; };
+template <> struct Word<4> { typedef uint32_t t; };
+
+// E consecutive reals of storage type S <-> compute values (one aligned word).
+template <class S, int E> struct Chunk {
+  typedef typename Word<E * (int)sizeof(S)>::t W;
+  template <class T> __device__ static inline void ld(const S* __restrict__ p, T* v) {
+    const W w = *reinterpret_cast<const W*>(p);
+    S e[E];
+    __builtin_memcpy(e, &w, sizeof(e));
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = (T)Store<S>::to(e[k]);
+  }
+  template <class T> __device__ static inline void st(S* __restrict__ p, const T* v) {
+    S e[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) e[k] = Store<S>::from((typename Store<S>::compute)v[k]);
+    W w;
+    __builtin_memcpy(&w, e, sizeof(e));
+    *reinterpret_cast<W*>(p) = w;
+  }
+};
+
+template <class A, class B, class C = A>
+struct ChunkWidth {
+  static constexpr int maxb = sizeof(A) > sizeof(B) ? (sizeof(A) > sizeof(C) ? sizeof(A) : sizeof(C))
+                                                     : (sizeof(B) > sizeof(C) ? sizeof(B) : sizeof(C));
+  static constexpr int e = 16 / maxb;
+};
+
+// Whether arrays of storage type S at these addresses, with right-hand-side
+// stride rs reals, can be walked in 16-byte words.
+template <class S> inline bool vec_ok(long rs, std::initializer_list<const void*> ptrs) {
+  if (((rs * (long)sizeof(S)) & 15) != 0) return false;
+  for (const void* q : ptrs)
+    if (reinterpret_cast<uintptr_t>(q) & 15) return false;
+  return true;
+}
+
+// part[r*NB + blk] = sum over this block's share of a_r . b_r (all reals);
+// vec: both fields can be read in aligned words (see TILE).
 template <class SA, class SB>
 __global__ void __launch_bounds__(RT) k_dot(const SA* __restrict__ a, const SB* __restrict__ b,
-                                            long n, long rsa, long rsb, double* __restrict__ part) {
+                                            long n, long rsa, long rsb, double* __restrict__ part,
+                                            int vec) {
   __shared__ double sh[RT];
   const int r = blockIdx.y, NB = gridDim.x;
   const SA* ar = a + (long)r * rsa;
   const SB* br = b + (long)r * rsb;
   double acc = 0;
-  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)NB * RT)
+  constexpr int E = ChunkWidth<SA, SB>::e;
+  const long nt = vec ? n / TILE : 0;
+  const int lane = threadIdx.x & 63;
+  const long t1 = nt * (blockIdx.x + 1) / NB;   // this block's contiguous range of tiles
+  for (long t = nt * blockIdx.x / NB + (threadIdx.x >> 6); t < t1; t += RT / 64) {
+#pragma unroll
+    for (int j = 0; j < 8 / E; ++j) {
+      const long i = t * TILE + j * 64 * E + lane * E;
+      double x[E], y[E];
+      Chunk<SA, E>::ld(ar + i, x);
+      Chunk<SB, E>::ld(br + i, y);
+#pragma unroll
+      for (int k = 0; k < E; ++k) acc += x[k] * y[k];
+    }
+  }
+  for (long i = TILE * nt + (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)NB * RT)
     acc += rd(ar, i) * rd(br, i);
   const double t = block_sum(acc, sh);
   if (threadIdx.x == 0) part[(long)r * NB + blockIdx.x] = t;
@@ -131,7 +198,7 @@ __global__ void __launch_bounds__(RT) k_update_xr(SX* __restrict__ x, SR* __rest
                                                   const SP* __restrict__ p,
                                                   const SP* __restrict__ Ap, long n, long rs,
                                                   const RhsState* __restrict__ st,
-                                                  double* __restrict__ part) {
+                                                  double* __restrict__ part, int vec) {
   __shared__ double sh[RT];
   typedef typename Store<SR>::compute T;
   const int q = blockIdx.y, NB = gridDim.x;
@@ -146,7 +213,31 @@ __global__ void __launch_bounds__(RT) k_update_xr(SX* __restrict__ x, SR* __rest
   const SP* pr = p + (long)q * rs;
   const SP* ar = Ap + (long)q * rs;
   double acc = 0;
-  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)NB * RT) {
+  constexpr int E = ChunkWidth<SX, SR, SP>::e;
+  const long nt = vec ? n / TILE : 0;
+  const int lane = threadIdx.x & 63;
+  const long t1 = nt * (blockIdx.x + 1) / NB;   // this block's contiguous range of tiles
+  for (long t = nt * blockIdx.x / NB + (threadIdx.x >> 6); t < t1; t += RT / 64) {
+#pragma unroll
+    for (int j = 0; j < 8 / E; ++j) {
+      const long i = t * TILE + j * 64 * E + lane * E;
+      T pv[E], av[E], xv[E], rv[E];
+      Chunk<SP, E>::ld(pr + i, pv);
+      Chunk<SP, E>::ld(ar + i, av);
+      Chunk<SX, E>::ld(xr + i, xv);
+      Chunk<SR, E>::ld(rr + i, rv);
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        xv[k] = xv[k] + al * pv[k];
+        rv[k] = rv[k] - al * av[k];
+      }
+      Chunk<SX, E>::st(xr + i, xv);
+      Chunk<SR, E>::st(rr + i, rv);
+#pragma unroll
+      for (int k = 0; k < E; ++k) acc += (double)rv[k] * (double)rv[k];
+    }
+  }
+  for (long i = TILE * nt + (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)NB * RT) {
     const T pv = (T)Store<SP>::to(pr[i]);
     const T av = (T)Store<SP>::to(ar[i]);
     xr[i] = Store<SX>::from((T)Store<SX>::to(xr[i]) + al * pv);
@@ -180,7 +271,8 @@ __global__ void __launch_bounds__(RT) k_beta(const double* __restrict__ part, in
 // p = r + beta p
 template <class SR, class SP>
 __global__ void __launch_bounds__(RT) k_update_p(const SR* __restrict__ r, SP* __restrict__ p,
-                                                 long n, long rs, const RhsState* __restrict__ st) {
+                                                 long n, long rs, const RhsState* __restrict__ st,
+                                                 int vec) {
   typedef typename Store<SR>::compute T;
   const int q = blockIdx.y, NB = gridDim.x;
   const RhsState& s = st[q];
@@ -188,7 +280,23 @@ __global__ void __launch_bounds__(RT) k_update_p(const SR* __restrict__ r, SP* _
   const T be = (T)s.beta;
   const SR* rr = r + (long)q * rs;
   SP* pr = p + (long)q * rs;
-  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)NB * RT)
+  constexpr int E = ChunkWidth<SR, SP>::e;
+  const long nt = vec ? n / TILE : 0;
+  const int lane = threadIdx.x & 63;
+  const long t1 = nt * (blockIdx.x + 1) / NB;   // this block's contiguous range of tiles
+  for (long t = nt * blockIdx.x / NB + (threadIdx.x >> 6); t < t1; t += RT / 64) {
+#pragma unroll
+    for (int j = 0; j < 8 / E; ++j) {
+      const long i = t * TILE + j * 64 * E + lane * E;
+      T rv[E], pv[E];
+      Chunk<SR, E>::ld(rr + i, rv);
+      Chunk<SP, E>::ld(pr + i, pv);
+#pragma unroll
+      for (int k = 0; k < E; ++k) pv[k] = rv[k] + be * pv[k];
+      Chunk<SP, E>::st(pr + i, pv);
+    }
+  }
+  for (long i = TILE * nt + (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)NB * RT)
     pr[i] = Store<SP>::from((T)Store<SR>::to(rr[i]) + be * (T)Store<SP>::to(pr[i]));
 }
 
@@ -332,7 +440,7 @@ __global__ void k_copy64(double* __restrict__ d, const S* __restrict__ s, long n
 int reduce_blocks(long n) {
   long nb = (n + 8191) / 8192;
   if (nb < 1) nb = 1;
-  if (nb > 512) nb = 512;
+  if (nb > 2048) nb = 2048;   // 8 blocks per CU at most; the second stage sums them in one block
   return (int)nb;
 }
 
@@ -387,7 +495,8 @@ int dot_re_im(qdwf_ctx* ctx, double* out_host, const void* x, const void* y, lon
     typedef decltype(tag) S;
     const S* a = reinterpret_cast<const S*>(x);
     const S* b = reinterpret_cast<const S*>(y);
-    hipLaunchKernelGGL((k_dot<S, S>), dim3(NB, nrhs), dim3(RT), 0, st, a, b, n, n, n, part);
+    const int vec = vec_ok<S>(n, {a, b}) ? 1 : 0;
+    hipLaunchKernelGGL((k_dot<S, S>), dim3(NB, nrhs), dim3(RT), 0, st, a, b, n, n, n, part, vec);
     hipLaunchKernelGGL(k_sum, dim3(nrhs), dim3(RT), 0, st, part, NB, res, 2);
     if (layout == QDWF_RIRI)
       hipLaunchKernelGGL((k_dot_im<S, S, QDWF_RIRI>), dim3(NB, nrhs), dim3(RT), 0, st, a, b, n, n, n,
@@ -482,16 +591,19 @@ struct Cg : Solver {
     int rc;
     S* p = at<S>(L.off_p);
     S* Ap = at<S>(L.off_ap);
+    // the workspace arrays start on 256-byte boundaries and n is a multiple of 24
+    const int vec_s = vec_ok<S>(n, {p, Ap}) ? 1 : 0;
+    const int vec_r = vec_ok<R>(n, {at<R>(L.off_xl), at<R>(L.off_rl)}) ? 1 : 0;
     if ((rc = apply_mdagm(ctx, inner, layout, Ap, p, at<S>(L.off_v), at<S>(L.off_t1),
                           at<S>(L.off_t2), nrhs, n, st)))
       return rc;
-    hipLaunchKernelGGL((k_dot<S, S>), grid(), dim3(RT), 0, st, p, Ap, n, n, n, part());
+    hipLaunchKernelGGL((k_dot<S, S>), grid(), dim3(RT), 0, st, p, Ap, n, n, n, part(), vec_s);
     hipLaunchKernelGGL(k_alpha, dim3(nrhs), dim3(RT), 0, st, part(), NB, d_state);
     hipLaunchKernelGGL((k_update_xr<R, R, S>), grid(), dim3(RT), 0, st, at<R>(L.off_xl),
-                       at<R>(L.off_rl), p, Ap, n, n, d_state, part());
+                       at<R>(L.off_rl), p, Ap, n, n, d_state, part(), vec_s && vec_r);
     hipLaunchKernelGGL(k_beta, dim3(nrhs), dim3(RT), 0, st, part(), NB, d_state, delta2);
     hipLaunchKernelGGL((k_update_p<R, S>), grid(), dim3(RT), 0, st, at<R>(L.off_rl), p, n, n,
-                       d_state);
+                       d_state, vec_s && vec_r);
     QDWF_HIP(hipGetLastError());
     hop_applications += 4;
     return QDWF_OK;
@@ -546,7 +658,8 @@ struct Cg : Solver {
     hop_applications = 0;
     QDWF_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_pin), sizeof(RhsState) * nrhs));
     QDWF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    hipLaunchKernelGGL((k_dot<double, double>), grid(), dim3(RT), 0, st, b, b, n, rs_b, rs_b, part());
+    hipLaunchKernelGGL((k_dot<double, double>), grid(), dim3(RT), 0, st, b, b, n, rs_b, rs_b, part(),
+                       vec_ok<double>(rs_b, {b}) ? 1 : 0);
     hipLaunchKernelGGL(k_init_state, dim3(nrhs), dim3(RT), 0, st, d_state, part(), NB, nrhs);
     hipLaunchKernelGGL((k_zero<R>), grid(), dim3(RT), 0, st, at<R>(L.off_xl), n, n);
     if (!prm.x0_is_guess) hipLaunchKernelGGL((k_zero<double>), grid(), dim3(RT), 0, st, xh, n, rs_x);
