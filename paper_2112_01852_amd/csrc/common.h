@@ -149,6 +149,7 @@ namespace qdwf {
 //   h      = D_h   chi          (dagger = 0, chi = A in)  or
 //   h      = A^dag D_h^dag in   (dagger = 1)
 //   out    = hop_scale * h + [epi] (alpha z + beta C z)   (C^dag when dagger)
+//   out    = hop_scale * M_ee^-1 h  (M_ee^-dag when dagger)  with minv = 1
 // in[p] is the half field of parity 1-p feeding output parity p; z[p] is at
 // parity p. rhs strides are in reals.
 struct HopArgs {
@@ -159,6 +160,7 @@ struct HopArgs {
   int par0, npar;
   int nrhs;
   int epi;
+  int minv;   // 1: apply M_ee^-1 (M_ee^-dag when dagger) to the result; Ls = 16, epi = 0
   double hop_scale, alpha, beta;
 };
 int launch_hop(qdwf_ctx* ctx, int prec, int layout, int dagger, const HopArgs& a,

@@ -38,8 +38,9 @@ struct HopK {
   long rs_in, rs_out, rs_z, plane;
   int Vh, Ls, nrhs, par0, npar;
   int nsb, nrb, gpw, nrblk;
-  int epi, xcd;
+  int epi, xcd, minv;
   double c_over_b, mf, hop_scale_b, alpha, beta;
+  double rpow[4];      // (-beta/alpha)^(2^j), j < 4: the M_ee^-1 scan
 };
 
 __device__ inline int xcd_remap(int bid, int nb) {
@@ -89,38 +90,44 @@ template <bool DPP16> struct SShift {
 // s_nop covers the two wait states a DPP read needs after a VALU write of the
 // same register, which the compiler does not track through inline assembly.
 // FP64 has no row rotate on 64-bit operands, so each half is moved first.
-__device__ inline int dpp_ror1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x121, 0xF, 0xF, false); }
-__device__ inline int dpp_ror15(int v) { return __builtin_amdgcn_mov_dpp(v, 0x12F, 0xF, 0xF, false); }
+template <int R> __device__ inline int dpp_ror(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x120 + R, 0xF, 0xF, false);
+}
+// v_fmac_f32 with its first source read through a DPP row rotate by R lanes
+#define QDWF_FMAC_ROR(R)                                                              \
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_ror:" #R " row_mask:0xf bank_mask:0xf" \
+      : "+v"(a) : "v"(x), "v"(c))
 template <> struct SShift<true> {
   int src_m, src_p;
-  __device__ inline float fm(float c, float x, float a) const {
-    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_ror:1 row_mask:0xf bank_mask:0xf"
-        : "+v"(a) : "v"(x), "v"(c));
+  // a + c x(lane - R), R = 1..15, within the 16-lane row
+  template <int R> __device__ inline float fr(float c, float x, float a) const {
+    static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 12 || R == 14 || R == 15,
+                  "rotation not instantiated");
+    if constexpr (R == 1) QDWF_FMAC_ROR(1);
+    else if constexpr (R == 2) QDWF_FMAC_ROR(2);
+    else if constexpr (R == 4) QDWF_FMAC_ROR(4);
+    else if constexpr (R == 8) QDWF_FMAC_ROR(8);
+    else if constexpr (R == 12) QDWF_FMAC_ROR(12);
+    else if constexpr (R == 14) QDWF_FMAC_ROR(14);
+    else QDWF_FMAC_ROR(15);
     return a;
   }
-  __device__ inline float fp(float c, float x, float a) const {
-    asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_ror:15 row_mask:0xf bank_mask:0xf"
-        : "+v"(a) : "v"(x), "v"(c));
-    return a;
-  }
-  __device__ inline double fm(double c, double x, double a) const {
+  template <int R> __device__ inline double fr(double c, double x, double a) const {
     const long long b = __double_as_longlong(x);
-    const int lo = dpp_ror1((int)b), hi = dpp_ror1((int)(b >> 32));
+    const int lo = dpp_ror<R>((int)b), hi = dpp_ror<R>((int)(b >> 32));
     return fmac(c, __longlong_as_double(((long long)hi << 32) | (unsigned int)lo), a);
   }
-  __device__ inline double fp(double c, double x, double a) const {
-    const long long b = __double_as_longlong(x);
-    const int lo = dpp_ror15((int)b), hi = dpp_ror15((int)(b >> 32));
-    return fmac(c, __longlong_as_double(((long long)hi << 32) | (unsigned int)lo), a);
-  }
+  template <class T> __device__ inline T fm(T c, T x, T a) const { return fr<1>(c, x, a); }
+  template <class T> __device__ inline T fp(T c, T x, T a) const { return fr<15>(c, x, a); }
 };
+#undef QDWF_FMAC_ROR
 
 // Target occupancy (waves per SIMD) the register allocator plans for: two for
 // 32- and 64-bit storage, whose arithmetic needs the registers to keep two
 // directions' neighbour loads in flight, three for 16-bit storage.
 template <class S> struct WavesPerEU { static constexpr int v = sizeof(S) >= 4 ? 2 : 3; };
 
-template <class S, int LAYOUT, bool DAG, bool DPP16>
+template <class S, int LAYOUT, bool DAG, bool DPP16, bool MINV>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_kernel(HopK k) {
   typedef typename Store<S>::compute T;
@@ -242,7 +249,33 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_ker
 #pragma unroll
     for (int i = 0; i < 24; ++i) acc[i] = tmp[i];
   }
-  const T hs = (T)k.hop_scale_b;   // hop scale times b
+  if constexpr (MINV) {
+    {
+      // out = M_ee^-1 (or M_ee^-dag) applied to the hop result, across the 16
+      // slices of the row: (alpha + beta S)^-1 on each chirality is a cyclic
+      // geometric series in S, summed by doubling (steps 1, 2, 4, 8), with -mf
+      // on the terms that wrap; its common factor is folded into the scale.
+      // M_ee: upper spins see S_d (slice s - d), lower spins S_u (s + d);
+      // the adjoint swaps them.
+      auto scan = [&](auto Jc) {
+        constexpr int J = decltype(Jc)::value;
+        constexpr int Dd = 1 << J;
+        const T rp = (T)k.rpow[J];
+        const T cdn = (s - Dd < 0) ? rp * (-mf) : rp;    // source slice s - d
+        const T cup = (s + Dd >= 16) ? rp * (-mf) : rp;  // source slice s + d
+#pragma unroll
+        for (int i = 0; i < 12; ++i)
+          acc[i] = DAG ? sh.template fr<16 - Dd>(cup, acc[i], acc[i])
+                       : sh.template fr<Dd>(cdn, acc[i], acc[i]);
+#pragma unroll
+        for (int i = 12; i < 24; ++i)
+          acc[i] = DAG ? sh.template fr<Dd>(cdn, acc[i], acc[i])
+                       : sh.template fr<16 - Dd>(cup, acc[i], acc[i]);
+      };
+      scan(IC<0>()); scan(IC<1>()); scan(IC<2>()); scan(IC<3>());
+    }
+  }
+  const T hs = (T)k.hop_scale_b;   // hop scale times b (and the M_ee^-1 factor)
   if (k.epi) {
     const S* zf = reinterpret_cast<const S*>(k.z[p]) + (long)rc * k.rs_z;
     T z[24];
@@ -272,7 +305,7 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_ker
   }
 }
 
-template <class S, int LAYOUT, bool DAG, bool DPP16>
+template <class S, int LAYOUT, bool DAG, bool DPP16, bool MINV>
 int run_hop_k(qdwf_ctx* ctx, int prec, const HopArgs& a, hipStream_t st, const HopShape& sh) {
   typedef typename Store<S>::compute T;
   const Geom& g = ctx->g;
@@ -294,19 +327,34 @@ int run_hop_k(qdwf_ctx* ctx, int prec, const HopArgs& a, hipStream_t st, const H
   k.mf = ctx->act.mf;
   k.hop_scale_b = a.hop_scale * ctx->act.b;
   k.alpha = a.alpha; k.beta = a.beta;
+  k.minv = MINV;
+  if (MINV) {
+    if (a.epi) return fail(QDWF_EINVAL, "fused M_ee^-1 takes no epilogue term");
+    const double al = ctx->act.b * (4.0 - ctx->act.M5) + 1.0;
+    const double be = ctx->act.c * (4.0 - ctx->act.M5) - 1.0;
+    double r = -be / al;
+    for (int j = 0; j < 4; ++j) { k.rpow[j] = r; r *= r; }
+    // r is now (-beta/alpha)^16 = (-beta/alpha)^Ls
+    k.hop_scale_b /= al * (1.0 + ctx->act.mf * r);
+  } else {
+    for (int j = 0; j < 4; ++j) k.rpow[j] = 0.0;
+  }
   const size_t lds = (size_t)8 * LinkStride<T>::v * k.nsb * sizeof(T) + (size_t)8 * k.nsb * sizeof(int) +
                     (size_t)sh.lds_pad;
   if (lds > 64 * 1024) return fail(QDWF_EINVAL, "hop launch shape needs %zu bytes of LDS", lds);
   dim3 grid(nsblk * k.nrblk * a.npar), block(sh.threads);
-  hipLaunchKernelGGL((hop_kernel<S, LAYOUT, DAG, DPP16>), grid, block, lds, st, k);
+  hipLaunchKernelGGL((hop_kernel<S, LAYOUT, DAG, DPP16, MINV>), grid, block, lds, st, k);
   QDWF_HIP(hipGetLastError());
   return QDWF_OK;
 }
 
 template <class S, int LAYOUT, bool DAG>
 int run_hop(qdwf_ctx* ctx, int prec, const HopArgs& a, hipStream_t st, const HopShape& sh) {
-  if (ctx->g.Ls == 16) return run_hop_k<S, LAYOUT, DAG, true>(ctx, prec, a, st, sh);
-  return run_hop_k<S, LAYOUT, DAG, false>(ctx, prec, a, st, sh);
+  if (ctx->g.Ls == 16)
+    return a.minv ? run_hop_k<S, LAYOUT, DAG, true, true>(ctx, prec, a, st, sh)
+                  : run_hop_k<S, LAYOUT, DAG, true, false>(ctx, prec, a, st, sh);
+  if (a.minv) return fail(QDWF_EINVAL, "fused M_ee^-1 needs Ls = 16");
+  return run_hop_k<S, LAYOUT, DAG, false, false>(ctx, prec, a, st, sh);
 }
 
 }  // namespace

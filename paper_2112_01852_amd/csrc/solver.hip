@@ -469,12 +469,28 @@ int apply_hop_parity(qdwf_ctx* ctx, int prec, int layout, int dagger, int out_pa
 int apply_mpc(qdwf_ctx* ctx, int prec, int layout, int dagger, void* out, const void* in,
               void* te1, void* te2, int nrhs, long rs, hipStream_t st) {
   int rc;
-  // te1 = M_eo in  (or (M_oe)^dag in)
-  if ((rc = apply_hop_parity(ctx, prec, layout, dagger, QDWF_EVEN, te1, in, nullptr, -0.5, nrhs, rs, st)))
-    return rc;
-  if ((rc = launch_local(ctx, prec, layout, dagger ? MAT_MEEINV_DAG : MAT_MEEINV, te2, te1, 1, 0, rs,
-                         nrhs, st)))
-    return rc;
+  if (ctx->g.Ls == 16) {
+    // te2 = M_ee^-1 M_eo in (or M_ee^-dag (M_oe)^dag in) in one launch: the
+    // hop's 16 slices of a site share a DPP row, where M_ee^-1 is a scan
+    HopArgs a = {};
+    a.in[QDWF_EVEN] = in;
+    a.out[QDWF_EVEN] = te2;
+    a.rs_in = a.rs_out = a.rs_z = rs;
+    a.par0 = QDWF_EVEN;
+    a.npar = 1;
+    a.nrhs = nrhs;
+    a.hop_scale = -0.5;
+    a.minv = 1;
+    if ((rc = launch_hop(ctx, prec, layout, dagger, a, st))) return rc;
+  } else {
+    // te1 = M_eo in  (or (M_oe)^dag in), then te2 = M_ee^-1 te1
+    if ((rc = apply_hop_parity(ctx, prec, layout, dagger, QDWF_EVEN, te1, in, nullptr, -0.5, nrhs,
+                               rs, st)))
+      return rc;
+    if ((rc = launch_local(ctx, prec, layout, dagger ? MAT_MEEINV_DAG : MAT_MEEINV, te2, te1, 1, 0,
+                           rs, nrhs, st)))
+      return rc;
+  }
   // out = M_oo in - M_oe te2 = alpha in + beta C in + 1/2 D_h A te2
   return apply_hop_parity(ctx, prec, layout, dagger, QDWF_ODD, out, te2, in, +0.5, nrhs, rs, st);
 }
