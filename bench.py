@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 # WRITE_SIZE passes scaled by a 2 GiB copy (profiles/hop_f32_riri_32x32x32x32x16.md),
 # keyed by the hash of the kernel source they were taken with; any other
 # source reports null until it is profiled again.
-MEASURED_TRAFFIC = {"5a1f326105feae65": 5.7824e9}
+MEASURED_TRAFFIC = {"9ad94b53cee744f3": 5.7807e9}
 FLOPS_PER_SITE = 1320        # Table 3 (real flops per 5D site per hop)
 MOBIUS = dict(M5=1.8, mf=0.01, b=1.5, c=0.5)
 
@@ -276,8 +276,10 @@ def solver_bench(args, torch, q, I):
     bo = D.pack(b, q.QDWF_F64, q.QDWF_RIRI, q.QDWF_ODD)
     del b, U
     out = {}
-    for name, inner in (("f64", q.QDWF_F64), ("f32", q.QDWF_F32), ("f16", q.QDWF_F16),
-                        ("bf16", q.QDWF_BF16)):
+    inners = (("f64", q.QDWF_F64), ("f32", q.QDWF_F32), ("f16", q.QDWF_F16), ("bf16", q.QDWF_BF16))
+    if args.inner:
+        inners = tuple(x for x in inners if x[0] in args.inner.split(","))
+    for name, inner in inners:
         ws = D.workspace(q.QDWF_OP_SOLVE, inner)
         x = D.field(q.QDWF_F64, q.QDWF_ODD)
         prm = q.solve_params(inner_prec=inner, layout=q.QDWF_RIRI, tol=1e-10, check_every=8,
@@ -439,6 +441,10 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.9,
                     help="offered load relative to one-at-a-time plain FP64 service")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--only", choices=["solver"], default=None,
+                    help="run only this row and print its JSON object (for profiling)")
+    ap.add_argument("--inner", default="",
+                    help="comma list of solver inner precisions (f64,f32,f16,bf16; default all)")
     ap.add_argument("--variants", default="",
                     help="comma list of Dslash variants to time (default all), e.g. f32_riri")
     args = ap.parse_args()
@@ -450,6 +456,9 @@ def main():
     from paper_2112_01852_amd import qdwf as q
     from paper_2112_01852_amd import inputs as I
     q.lib()
+    if args.only == "solver":
+        print(json.dumps({"solver_24x24x24x24x16": solver_bench(args, torch, q, I)}), flush=True)
+        return
     probe = copy_probe(torch)
     log("copy probe", probe)
     dres, sites = dslash_bench(args, torch, q, I)
