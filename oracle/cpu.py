@@ -74,26 +74,31 @@ class Action:
 _lib = None
 
 
+def load(path: str):
+    """ctypes handle of an oracle library at ``path`` with its signatures set."""
+    L = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    A = ctypes.POINTER(_Action)
+    I = ctypes.c_int
+    L.or_gammas.argtypes = [P]
+    L.or_hop.argtypes = [A, P, P, P, I]
+    L.or_dwf.argtypes = [A, P, P, P, I]
+    L.or_dwf_sites.argtypes = [A, P, P, P, ctypes.c_int64, P, I]
+    L.or_local.argtypes = [A, P, P, ctypes.c_double, ctypes.c_double, I]
+    L.or_mee.argtypes = [A, P, P, I, I]
+    L.or_deo.argtypes = [A, P, P, P, I, I]
+    L.or_mpc.argtypes = [A, P, P, P, I]
+    L.or_cg.argtypes = [A, P, P, P, ctypes.c_double, I, ctypes.POINTER(ctypes.c_double)]
+    L.or_cg.restype = I
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=False)
-        L = ctypes.CDLL(_LIB)
-        P = ctypes.c_void_p
-        A = ctypes.POINTER(_Action)
-        I = ctypes.c_int
-        L.or_gammas.argtypes = [P]
-        L.or_hop.argtypes = [A, P, P, P, I]
-        L.or_dwf.argtypes = [A, P, P, P, I]
-        L.or_dwf_sites.argtypes = [A, P, P, P, ctypes.c_int64, P, I]
-        L.or_local.argtypes = [A, P, P, ctypes.c_double, ctypes.c_double, I]
-        L.or_mee.argtypes = [A, P, P, I, I]
-        L.or_deo.argtypes = [A, P, P, P, I, I]
-        L.or_mpc.argtypes = [A, P, P, P, I]
-        L.or_cg.argtypes = [A, P, P, P, ctypes.c_double, I, ctypes.POINTER(ctypes.c_double)]
-        L.or_cg.restype = I
-        _lib = L
+        _lib = load(_LIB)
     return _lib
 
 

@@ -361,7 +361,7 @@ def test_cg_matches_dense_solve(tiny):
     a, U, psi = tiny
     Mpc, odd = dense.mpc_matrix(a, U)
     b = cpu.restrict(psi, a.L, 1)
-    x, it, res = cpu.cg(a, U, b, tol=1e-13)
+    x, it, res = cpu.cg(a, U, b, tol=1e-13, max_iter=1000)
     A = Mpc.conj().T @ Mpc
     xs = np.linalg.solve(A, b.ravel()[odd])
     assert res < 1e-12
