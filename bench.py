@@ -12,7 +12,7 @@ solves/s on 24^4 x 16 with smoothed links, and the FP64 CPU oracle timed on
 the host cores on the same workload, and the paper's Table 2 domain-wall
 volumes (Shamir D and the even-odd hop, FP64 and FP32) and the Wilson Dslash
 kernel at its Table 1 volumes, and the per-site SU(3) product and triad
-streaming probes.
+streaming probes, and D applied as a 4-slab domain decomposition on one GPU.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-solver] [--no-cpu]
 """
@@ -215,6 +215,46 @@ def wilson_shapes_bench(args, torch, q, I):
             del fin, fout
         out[key] = row
         log("wilson shape", key, row)
+        D.close()
+        del psi
+        torch.cuda.empty_cache()
+    return out
+
+
+def split_bench(args, torch, q, I):
+    """D applied as a 4-slab domain decomposition along t (face packing,
+    half-spinor exchange by device copy, interior hop, boundary update) next
+    to the undivided D, the emulated form of the paper's 1 vs 4 rank columns
+    (Table 2), on 16^3x32 x 16 and 32^4 x 16, Mobius, RIRI."""
+    out = {}
+    for L, Ls, precs in (((16, 16, 16, 32), 16, (("f64", q.QDWF_F64), ("f32", q.QDWF_F32))),
+                         ((32, 32, 32, 32), 16, (("f32", q.QDWF_F32),))):
+        U = I.gauge_field(L, "haar", 2300, dtype=np.complex64)
+        psi = torch.from_numpy(I.gaussian_spinor(L, Ls, 2301, dtype=np.complex64)).cuda()
+        D = q.Dirac(L, Ls, **MOBIUS)
+        D.set_gauge(torch.from_numpy(U))
+        sites = D.V * Ls
+        key = "%dx%dx%dx%dx%d" % (L + (Ls,))
+        row = {}
+        for name, prec in precs:
+            fin = D.field(prec, q.QDWF_FULL, zero=False)
+            q.qdwf_pack_spinor(D.ctx, fin, prec, q.QDWF_RIRI, psi, q.QDWF_FULL)
+            fout = D.field(prec, q.QDWF_FULL, zero=False)
+            steps = max(args.steps // 2, 5)
+            ms1 = time_launches(lambda: q.qdwf_apply_D(D.ctx, fout, fin, 0, prec, q.QDWF_RIRI),
+                                steps, 3, torch)
+            ws = torch.empty(q.qdwf_split_workspace_bytes(D.ctx, 4, prec), dtype=torch.uint8,
+                             device="cuda")
+            q.qdwf_split_prepare(D.ctx, 4, prec, ws)
+            ms4 = time_launches(lambda: q.qdwf_apply_D_split(D.ctx, fout, fin, 4, prec, q.QDWF_RIRI, ws),
+                                steps, 3, torch)
+            row[name] = {"D_1slab_ms": ms1, "D_4slab_ms": ms4,
+                         "D_1slab_gflops": FLOPS_PER_SITE * sites / (ms1 * 1e-3) / 1e9,
+                         "D_4slab_gflops": FLOPS_PER_SITE * sites / (ms4 * 1e-3) / 1e9,
+                         "overhead": ms4 / ms1 - 1.0}
+            del fin, fout, ws
+        out[key] = row
+        log("split", key, row)
         D.close()
         del psi
         torch.cuda.empty_cache()
@@ -469,6 +509,7 @@ def main():
     paper = None if args.no_paper else paper_shapes_bench(args, torch, q, I)
     wilson = None if args.no_paper else wilson_shapes_bench(args, torch, q, I)
     streaming = None if args.no_paper else streaming_bench(args, torch, q, I)
+    split = None if args.no_paper else split_bench(args, torch, q, I)
     solver = None if args.no_solver else solver_bench(args, torch, q, I)
     multi = None if args.no_multi else multi_rhs_bench(args, torch, q, I)
     served = None if args.no_serve else serving_bench(args, torch, q)
@@ -502,6 +543,7 @@ def main():
         "paper_dwf_shapes": paper,
         "paper_wilson_shapes": wilson,
         "streaming_probes": streaming,
+        "domain_split_4": split,
         "solver_24x24x24x24x16": solver,
         "multi_rhs_16x16x16x16x16_n24": multi,
         "serving": served,

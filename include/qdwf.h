@@ -212,6 +212,25 @@ int qdwf_apply_MdagM(qdwf_ctx* ctx, void* out, const void* in, int prec, int lay
 /* Device workspace size in bytes for an operation (see QDWF_OP_*). */
 size_t qdwf_workspace_bytes(const qdwf_ctx* ctx, int op, int prec, int nrhs);
 
+/* ---- domain decomposition emulated on one GPU --------------------------- */
+/* D applied as a run split into `ranks` slabs along t would apply it (the
+ * paper's 4-rank runs, Section 4.2): each slab packs its two t-faces into
+ * spin-projected half spinors (12 reals per face site and slice), the half
+ * spinors are exchanged (device copies), the hop runs on the slabs with the
+ * cross-slab links zeroed, and the face sites add the received hops.
+ * ranks must divide Lt into slabs of at least 2 slices; ranks = 1 exercises
+ * the same path across the periodic boundary. Full fields, one right-hand
+ * side, D only (no dagger); the result equals qdwf_apply_D up to the order
+ * of summation on face sites.
+ * ws: qdwf_split_workspace_bytes(ctx, ranks, prec) bytes, filled once by
+ * qdwf_split_prepare for this ranks and prec (and again after each
+ * qdwf_set_gauge); it holds the cut links, a site table and the face
+ * buffers. qdwf_split_prepare synchronises `stream`. */
+size_t qdwf_split_workspace_bytes(const qdwf_ctx* ctx, int ranks, int prec);
+int qdwf_split_prepare(qdwf_ctx* ctx, int ranks, int prec, void* ws, void* stream);
+int qdwf_apply_D_split(qdwf_ctx* ctx, void* out, const void* in, int ranks, int prec, int layout,
+                       void* ws, void* stream);
+
 /* ---- streaming probes (no context) ------------------------------------- */
 /* Per-site SU(3) product of the Benchmark_su3 study (Section 4.2):
  * C[i] = A[i] B[i] for i < n, each a 3x3 complex matrix stored row-major with

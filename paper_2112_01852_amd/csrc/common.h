@@ -87,18 +87,6 @@ inline size_t prec_bytes(int prec) {
   }
 }
 
-// Calls f.template operator()<S>() with S the storage type of `prec`.
-template <class F>
-int dispatch_prec(int prec, F&& f) {
-  switch (prec) {
-    case QDWF_F64: return f.template operator()<double>();
-    case QDWF_F32: return f.template operator()<float>();
-    case QDWF_F16: return f.template operator()<_Float16>();
-    case QDWF_BF16: return f.template operator()<bf16>();
-  }
-  return fail(QDWF_EINVAL, "unknown precision %d", prec);
-}
-
 // -------------------------------------------------------------- geometry
 struct Geom {
   int L[4];
@@ -162,6 +150,7 @@ struct HopArgs {
   int epi;
   int minv;   // 1: apply M_ee^-1 (M_ee^-dag when dagger) to the result; Ls = 16, epi = 0
   double hop_scale, alpha, beta;
+  const void* links;   // links to use instead of the context's (nullptr: the context's)
 };
 int launch_hop(qdwf_ctx* ctx, int prec, int layout, int dagger, const HopArgs& a,
                hipStream_t st, const HopShape* shape = nullptr);

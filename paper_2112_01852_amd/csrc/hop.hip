@@ -311,7 +311,7 @@ int run_hop_k(qdwf_ctx* ctx, int prec, const HopArgs& a, hipStream_t st, const H
   const Geom& g = ctx->g;
   HopK k;
   for (int i = 0; i < 2; ++i) { k.in[i] = a.in[i]; k.out[i] = a.out[i]; k.z[i] = a.z[i]; }
-  k.links = ctx->d_links[prec];
+  k.links = a.links ? a.links : ctx->d_links[prec];
   k.nbr = ctx->d_nbr;
   k.rs_in = a.rs_in; k.rs_out = a.rs_out; k.rs_z = a.rs_z;
   k.plane = g.n5h;

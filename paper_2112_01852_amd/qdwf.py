@@ -76,6 +76,9 @@ _SIG = {
     "qdwf_apply_D": ([_P, _P, _P, _I, _I, _I, _I, _P], _I),
     "qdwf_apply_Mee": ([_P, _P, _P, _I, _I, _I, _I, _I, _I, _P], _I),
     "qdwf_apply_Deo": ([_P, _P, _P, _I, _I, _I, _I, _I, _P], _I),
+    "qdwf_split_workspace_bytes": ([_P, _I, _I], ctypes.c_size_t),
+    "qdwf_split_prepare": ([_P, _I, _I, _P, _P], _I),
+    "qdwf_apply_D_split": ([_P, _P, _P, _I, _I, _I, _P, _P], _I),
     "qdwf_su3_mul": ([_P, _P, _P, ctypes.c_int64, _I, _I, _P], _I),
     "qdwf_triad": ([_P, _P, _P, ctypes.c_double, ctypes.c_int64, _I, _I, _P], _I),
     "qdwf_apply_Dh": ([_P, _P, _P, _I, _I, _I, _I, _I, _P], _I),
@@ -228,6 +231,19 @@ def qdwf_apply_Dh(ctx, out, inp, subset, dagger, prec, layout, nrhs=1, stream=No
 def qdwf_apply_Dw(ctx, out, inp, mass, dagger, prec, layout, nrhs=1, stream=None):
     _check(lib().qdwf_apply_Dw(ctx, _ptr(out, "out"), _ptr(inp, "in"), float(mass), int(dagger),
                                int(prec), int(layout), int(nrhs), _stream(stream)))
+
+
+def qdwf_split_workspace_bytes(ctx, ranks, prec) -> int:
+    return int(lib().qdwf_split_workspace_bytes(ctx, int(ranks), int(prec)))
+
+
+def qdwf_split_prepare(ctx, ranks, prec, ws, stream=None):
+    _check(lib().qdwf_split_prepare(ctx, int(ranks), int(prec), _ptr(ws, "ws"), _stream(stream)))
+
+
+def qdwf_apply_D_split(ctx, out, inp, ranks, prec, layout, ws, stream=None):
+    _check(lib().qdwf_apply_D_split(ctx, _ptr(out, "out"), _ptr(inp, "in"), int(ranks), int(prec),
+                                    int(layout), _ptr(ws, "ws"), _stream(stream)))
 
 
 def qdwf_su3_mul(C, A, B, n, prec, device=0, stream=None):
