@@ -45,7 +45,9 @@
  * back to back. Two layouts of the 24 reals c = (spin*3 + colour)*2 + re/im
  * exist (Section 4.3 compares the same two choices for SVE registers):
  *   QDWF_RIRI  interleaved complex, blocked over the slices of a 4D site in
- *              chunks of 4 reals: offset i*Ls*24 + (c/4)*Ls*4 + s*4 + c%4
+ *              chunks of 4 reals: offset i*Ls*24 + (c/4)*Ls*4 + s*4 + c%4;
+ *              for Ls = 1 over 16 consecutive sites (i/16 and i%16 in place
+ *              of i and s), which needs V/2 to be a multiple of 16
  *   QDWF_RRII  split planes: offset ((c%2)*12 + c/2)*(V/2)*Ls + i*Ls + s
  * Precisions give the storage type of a real; arithmetic is FP64 for QDWF_F64
  * and FP32 for the others (FP16/BF16 are storage only, rounded to nearest even).
@@ -100,7 +102,8 @@ extern "C" {
 /* ---- types ------------------------------------------------------------ */
 typedef struct {
   int32_t L[4];     /* extents x, y, z, t; each even and >= 2                 */
-  int32_t Ls;       /* fifth-dimension extent, 1 <= Ls <= 64 (1: 4D fields)    */
+  int32_t Ls;       /* fifth-dimension extent, 1 <= Ls <= 64 (1: 4D fields,    */
+                    /* V/2 a multiple of 16)                                    */
   int32_t bc[4];    /* +1 periodic, -1 antiperiodic per direction            */
   double M5;        /* domain-wall height                                    */
   double mf;        /* quark mass (wall coupling -mf)                        */

@@ -114,6 +114,8 @@ int qdwf_create(const qdwf_action* act, int device, qdwf_ctx** out) {
       return fail(QDWF_EINVAL, "bc[%d] = %d must be +1 or -1", mu, act->bc[mu]);
   }
   if (act->Ls < 1 || act->Ls > 64) return fail(QDWF_EINVAL, "Ls = %d must be in [1, 64]", act->Ls);
+  if (act->Ls == 1 && ((long)act->L[0] * act->L[1] * act->L[2] * act->L[3] / 2) % 16 != 0)
+    return fail(QDWF_EINVAL, "4D fields (Ls = 1) need a multiple of 16 sites per parity");
   const double V = (double)act->L[0] * act->L[1] * act->L[2] * act->L[3];
   if (V * act->Ls / 2 * 24 > 9.0e18 || V > 2.0e9) return fail(QDWF_EINVAL, "lattice too large");
   if (!(std::fabs(act->b) > 0.0) || !std::isfinite(act->b))

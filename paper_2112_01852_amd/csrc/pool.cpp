@@ -191,7 +191,7 @@ int qdwf_pool_submit(qdwf_pool* pool, const qdwf_request* req, uint64_t* id) {
   for (int mu = 0; mu < 4; ++mu)
     if (req->act.L[mu] < 2 || (req->act.L[mu] & 1) || (req->act.bc[mu] != 1 && req->act.bc[mu] != -1))
       return fail(QDWF_EINVAL, "bad lattice extent or boundary in direction %d", mu);
-  if (req->act.Ls < 1 || req->act.Ls > 64) return fail(QDWF_EINVAL, "Ls out of range");
+  if (req->act.Ls < 2 || req->act.Ls > 64) return fail(QDWF_EINVAL, "Ls out of range");
   PoolRequest* r = new (std::nothrow) PoolRequest();
   if (!r) return fail(QDWF_ENOMEM, "host allocation failed");
   r->id = pool->next_id++;

@@ -11,6 +11,10 @@
 //         a neighbour touches the fewest cache lines. The element order is
 //         the same in every precision, which lets the solver convert
 //         between precisions element by element.
+//         With Ls = 1 (4D fields) the same blocking runs over 16 consecutive
+//         sites instead: site i is slice i % 16 of block i / 16, so that the
+//         lanes of consecutive sites read contiguous runs (V/2 must then be a
+//         multiple of 16).
 //   RRII  split planes: 24 planes of n5h = (V/2)*Ls reals, plane
 //         (c & 1)*12 + c/2 ([re/im][spin][colour]), index i*Ls + s.
 //
@@ -22,7 +26,17 @@
 
 namespace qdwf {
 
+// Ls = 1: 16 consecutive sites play the role of the slices of a block.
+__host__ __device__ inline void riri_block(long& i, int& s, int& Ls) {
+  if (Ls == 1) {
+    s = (int)(i & 15);
+    i >>= 4;
+    Ls = 16;
+  }
+}
+
 __host__ __device__ inline long riri_offset(long i, int s, int c, int Ls) {
+  riri_block(i, s, Ls);
   return i * Ls * 24 + (long)(c >> 2) * Ls * 4 + (long)s * 4 + (c & 3);
 }
 
@@ -57,6 +71,7 @@ template <class S> struct SiteIO<S, QDWF_RRII> {
 template <> struct SiteIO<double, QDWF_RIRI> {
   __device__ static inline void load(const double* __restrict__ f, long i, int s, int Ls, long,
                                      double* v) {
+    riri_block(i, s, Ls);
     const double2* p = reinterpret_cast<const double2*>(f + i * Ls * 24 + (long)s * 4);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -69,6 +84,7 @@ template <> struct SiteIO<double, QDWF_RIRI> {
   }
   __device__ static inline void store(double* __restrict__ f, long i, int s, int Ls, long,
                                       const double* v) {
+    riri_block(i, s, Ls);
     double2* p = reinterpret_cast<double2*>(f + i * Ls * 24 + (long)s * 4);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -81,6 +97,7 @@ template <> struct SiteIO<double, QDWF_RIRI> {
 template <> struct SiteIO<float, QDWF_RIRI> {
   __device__ static inline void load(const float* __restrict__ f, long i, int s, int Ls, long,
                                      float* v) {
+    riri_block(i, s, Ls);
     const float4* p = reinterpret_cast<const float4*>(f + i * Ls * 24 + (long)s * 4);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -93,6 +110,7 @@ template <> struct SiteIO<float, QDWF_RIRI> {
   }
   __device__ static inline void store(float* __restrict__ f, long i, int s, int Ls, long,
                                       const float* v) {
+    riri_block(i, s, Ls);
     float4* p = reinterpret_cast<float4*>(f + i * Ls * 24 + (long)s * 4);
 #pragma unroll
     for (int k = 0; k < 6; ++k)
@@ -104,6 +122,7 @@ template <> struct SiteIO<float, QDWF_RIRI> {
 template <class S> struct SiteIO16 {
   __device__ static inline void load(const S* __restrict__ f, long i, int s, int Ls, long,
                                      float* v) {
+    riri_block(i, s, Ls);
     const uint2* p = reinterpret_cast<const uint2*>(f + i * Ls * 24 + (long)s * 4);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
@@ -116,6 +135,7 @@ template <class S> struct SiteIO16 {
   }
   __device__ static inline void store(S* __restrict__ f, long i, int s, int Ls, long,
                                       const float* v) {
+    riri_block(i, s, Ls);
     uint2* p = reinterpret_cast<uint2*>(f + i * Ls * 24 + (long)s * 4);
 #pragma unroll
     for (int k = 0; k < 6; ++k) {

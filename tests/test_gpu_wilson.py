@@ -4,7 +4,8 @@
 
 Tolerances (relative L2 over all reals, oracle on the original FP64 inputs):
 FP64 1e-13, FP32 1e-6, FP16/BF16 storage 5e-3. The lattices leave a partial
-last block of 256 lanes and, at 6x6x10x6, partial traversal tiles.
+last block of 256 lanes and, at 6x6x8x6, partial traversal tiles; 4D fields
+(Ls = 1) are blocked over 16 sites in the RIRI layout.
 """
 import numpy as np
 import pytest
@@ -16,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = {0: 1e-13, 1: 1e-6, 2: 5e-3, 3: 5e-3}
 SHAMIR = dict(M5=1.8, mf=0.01, b=1.0, c=0.0)
-CASES = [((6, 4, 4, 6), 1), ((6, 6, 10, 6), 1), ((4, 4, 2, 6), 8), ((4, 2, 4, 4), 16)]
+CASES = [((6, 4, 4, 6), 1), ((6, 6, 8, 6), 1), ((4, 4, 2, 6), 8), ((4, 2, 4, 4), 16)]
 
 
 def _rel(x, y):
@@ -111,3 +112,5 @@ def test_invalid_arguments(q):
     with pytest.raises(q.QdwfError):
         q.qdwf_apply_Dw(D.ctx, g, f, float("nan"), 0, q.QDWF_F32, q.QDWF_RIRI)
     D.close()
+    with pytest.raises(q.QdwfError):
+        q.qdwf_create(q.make_action((6, 6, 10, 6), 1))   # 1080 sites per parity: not a multiple of 16
