@@ -136,13 +136,16 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_ker
   T* su = reinterpret_cast<T*>(smem);                       // [nsb][8][LSTR]
   int* snb = reinterpret_cast<int*>(su + (size_t)8 * LSTR * k.nsb);   // [8][nsb]
 
-  // logical block: right-hand-side block fastest, then parity, then sites;
-  // the XCD remap hands each XCD a contiguous range of logical blocks
+  // logical block: parity fastest, then sites, then right-hand-side blocks,
+  // so the right-hand sides sweep the lattice one after another and the
+  // working set the caches see is one field at a time; the XCD remap hands
+  // each XCD a contiguous range of logical blocks
   const int L = k.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  const int rb = L % k.nrblk;
-  const int t1 = L / k.nrblk;
-  const int p = k.par0 + t1 % k.npar;
-  const int sb = t1 / k.npar;
+  const int nsblk = (k.Vh + k.nsb - 1) / k.nsb;
+  const int p = k.par0 + L % k.npar;
+  const int t1 = L / k.npar;
+  const int sb = t1 % nsblk;
+  const int rb = t1 / nsblk;
   const int q = 1 - p;
   const int cb0 = sb * k.nsb;
   const int Vh = k.Vh;
@@ -369,30 +372,18 @@ HopShape default_shape(const qdwf_ctx* ctx, int prec, int nrhs) {
   if (waves > 4) waves = 4;
   sh.threads = 64 * waves;
   sh.xcd = 1;
-  const int G = waves * gpw;
-  int nrb = 1;
-  for (int d = 1; d <= G; ++d)
-    if (G % d == 0 && d <= nrhs) nrb = d;
-  // keep at least 4 sites per block so the link staging amortises
-  while (nrb > 1 && G / nrb < 4) {
-    int nd = nrb - 1;
-    while (nd > 1 && G % nd) --nd;
-    nrb = nd;
-  }
-  sh.nrb = nrb;
+  // one right-hand side per block: with the right-hand sides outermost in the
+  // block order this measured faster than sharing the staged links between
+  // several right-hand sides of a block (the tuner still tries both)
+  sh.nrb = 1;
   sh.lds_pad = 0;
   if (const char* e = std::getenv("QDWF_HOP_LDS_PAD")) sh.lds_pad = std::atoi(e);
   if (const char* e = std::getenv("QDWF_HOP_THREADS")) {
     const int t = std::atoi(e);
-    if (t >= 64 && t <= 256 && t % 64 == 0) {
-      sh.threads = t;
-      const int G2 = (t / 64) * gpw;
-      sh.nrb = 1;
-      for (int d = 1; d <= G2; ++d)
-        if (G2 % d == 0 && d <= nrhs && G2 / d >= 4) sh.nrb = d;
-    }
+    if (t >= 64 && t <= 256 && t % 64 == 0) sh.threads = t;
   }
   (void)prec;
+  (void)nrhs;
   return sh;
 }
 
