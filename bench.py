@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 # WRITE_SIZE passes scaled by a 2 GiB copy (profiles/hop_f32_riri_32x32x32x32x16.md),
 # keyed by the hash of the kernel source they were taken with; any other
 # source reports null until it is profiled again.
-MEASURED_TRAFFIC = {"5e5a358d90e6f5dd": 5.7587e9}
+MEASURED_TRAFFIC = {"95d3505f5d76dfe2": 5.7791e9}
 FLOPS_PER_SITE = 1320        # Table 3 (real flops per 5D site per hop)
 MOBIUS = dict(M5=1.8, mf=0.01, b=1.5, c=0.5)
 
