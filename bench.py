@@ -30,11 +30,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
-# HBM bytes per launch of the FP32 full-D kernel, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE passes scaled by a 2 GiB copy (profiles/hop_f32_riri_32x32x32x32x16.md),
+# HBM bytes per launch of the FP32 full-D kernel (the t-sweep), from rocprofv3
+# FETCH_SIZE and WRITE_SIZE passes scaled by a 2 GiB copy
+# (profiles/sweep_f32_riri_32x32x32x32x16.md),
 # keyed by the hash of the kernel source they were taken with; any other
 # source reports null until it is profiled again.
-MEASURED_TRAFFIC = {"95d3505f5d76dfe2": 5.7791e9}
+MEASURED_TRAFFIC = {"dbf8b9874ab3040c": 6.5600e9}
 FLOPS_PER_SITE = 1320        # Table 3 (real flops per 5D site per hop)
 MOBIUS = dict(M5=1.8, mf=0.01, b=1.5, c=0.5)
 
@@ -46,8 +47,9 @@ def log(*a):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    # the kernel, its spinor I/O and the site traversal order built at create
-    for f in ("hop.hip", "common.h", "siteio.h", "api.cpp"):
+    # the kernels (t-sweep and checkerboard), their spinor I/O, the routing
+    # between them and the site traversal order built at create
+    for f in ("sweep.hip", "hop.hip", "hopcore.h", "common.h", "siteio.h", "api.cpp"):
         with open(os.path.join(HERE, "paper_2112_01852_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -125,6 +127,20 @@ def dslash_bench(args, torch, q, I):
                 "ms": ms, "gflops": FLOPS_PER_SITE * hs / (ms * 1e-3) / 1e9,
                 "algo_GBs": algorithmic_bytes_per_site(pb, Ls, True) * hs / (ms * 1e-3) / 1e9}
             log(f"Ddag/Deo {lname}", res[f"Ddag_{name}_{lname}"], res[f"Deo_{name}_{lname}"])
+            if layout == q.QDWF_RIRI:
+                # the same D through the checkerboard kernel, the t-sweep off
+                prev = os.environ.get("QDWF_SWEEP")
+                os.environ["QDWF_SWEEP"] = "0"
+                fn = lambda: q.qdwf_apply_D(D.ctx, fout, fin, 0, prec, layout)
+                ms = time_launches(fn, max(args.steps // 2, 3), 2, torch)
+                if prev is None:
+                    del os.environ["QDWF_SWEEP"]
+                else:
+                    os.environ["QDWF_SWEEP"] = prev
+                res[f"D_{name}_{lname}_checkerboard"] = {
+                    "ms": ms, "gflops": FLOPS_PER_SITE * sites / (ms * 1e-3) / 1e9,
+                    "algo_GBs": algorithmic_bytes_per_site(pb, Ls, False) * sites / (ms * 1e-3) / 1e9}
+                log("D checkerboard kernel", res[f"D_{name}_{lname}_checkerboard"])
         del fin, fout
         torch.cuda.empty_cache()
     D.close()

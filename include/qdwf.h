@@ -142,8 +142,11 @@ const char* qdwf_last_error(void);
 
 /* ---- lifecycle -------------------------------------------------------- */
 /* Validates the action and, on `device`, allocates the library-owned
- * neighbour tables (int32 [2][8][V/2]) and 5D-local matrices. Links are added
- * by qdwf_set_gauge. Distinct contexts are independent; one context must not
+ * neighbour tables (int32 [2][8][V/2]), the site index (int32 [V]), the
+ * 5D-local matrices and the link arrays (filled by qdwf_set_gauge). With
+ * Ls = 16 and Lx in {8, 16, 24, 32} it also allocates doubled links (the 8
+ * links of each site, 2 x 144 x V/2 reals) in FP32, FP16 and BF16 for the
+ * t-sweep form of qdwf_apply_D: 1.2 GB at 32^4. Distinct contexts are independent; one context must not
  * be used from two threads at once. */
 int qdwf_create(const qdwf_action* act, int device, qdwf_ctx** out);
 int qdwf_destroy(qdwf_ctx* ctx);
@@ -151,7 +154,7 @@ int qdwf_destroy(qdwf_ctx* ctx);
 /* Packs the canonical gauge field U (device pointer; complex128 when
  * canon_prec = QDWF_F64, complex64 when QDWF_F32) into library-owned link
  * arrays in every precision, per parity, with the boundary factors bc folded
- * into the links. Stream-ordered on `stream` (a hipStream_t, NULL = default). */
+ * into the links (and rebuilds the doubled links where the context has them). Stream-ordered on `stream` (a hipStream_t, NULL = default). */
 int qdwf_set_gauge(qdwf_ctx* ctx, const void* U, int canon_prec, void* stream);
 
 /* Number of reals in one right-hand side of an internal field of `subset`
@@ -171,7 +174,11 @@ int qdwf_unpack_spinor(qdwf_ctx* ctx, void* dst, int dst_prec, const void* src, 
 
 /* ---- operators (all asynchronous on `stream`; out must not alias in) --- */
 /* Full 5D domain-wall operator: out = D in (dagger = 0) or D^dag in
- * (dagger = 1). in, out: full fields, nrhs right-hand sides. */
+ * (dagger = 1). in, out: full fields, nrhs right-hand sides. With Ls = 16,
+ * the interleaved layout, 32- or 16-bit storage and 16- or 32-wide x rows it
+ * runs as a sweep of whole x-rows along t (same result up to FP32 rounding
+ * order); the environment variable QDWF_SWEEP=1 / 0 forces that form on
+ * (also for 8- and 24-wide rows) or off. */
 int qdwf_apply_D(qdwf_ctx* ctx, void* out, const void* in, int dagger, int prec, int layout,
                  int nrhs, void* stream);
 

@@ -236,6 +236,12 @@ int qdwf_create(const qdwf_action* act, int device, qdwf_ctx** out) {
   if (e == hipSuccess) e = hipMalloc(&c->d_mat64, sizeof(double) * c->h_mat.size());
   if (e == hipSuccess) e = hipMalloc(&c->d_mat32, sizeof(float) * m32.size());
   for (int p = 0; p < 4 && e == hipSuccess; ++p) e = hipMalloc(&c->d_links[p], link_reals * prec_bytes(p));
+  if (e == hipSuccess) e = hipMalloc(&c->d_idx, sizeof(int32_t) * c->h_idx.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(c->d_idx, c->h_idx.data(), sizeof(int32_t) * c->h_idx.size(), hipMemcpyHostToDevice);
+  if (sweep_geometry(g))
+    for (int p = QDWF_F32; p <= QDWF_BF16 && e == hipSuccess; ++p)
+      e = hipMalloc(&c->d_dlinks[p], 2 * link_reals * prec_bytes(p));
   if (e == hipSuccess)
     e = hipMemcpy(c->d_nbr, c->h_nbr.data(), sizeof(int32_t) * c->h_nbr.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)
@@ -259,8 +265,11 @@ int qdwf_destroy(qdwf_ctx* ctx) {
   if (ctx->d_site_lex) (void)hipFree(ctx->d_site_lex);
   if (ctx->d_mat64) (void)hipFree(ctx->d_mat64);
   if (ctx->d_mat32) (void)hipFree(ctx->d_mat32);
-  for (int p = 0; p < 4; ++p)
+  if (ctx->d_idx) (void)hipFree(ctx->d_idx);
+  for (int p = 0; p < 4; ++p) {
     if (ctx->d_links[p]) (void)hipFree(ctx->d_links[p]);
+    if (ctx->d_dlinks[p]) (void)hipFree(ctx->d_dlinks[p]);
+  }
   delete ctx;
   return QDWF_OK;
 }
@@ -272,6 +281,7 @@ int qdwf_set_gauge(qdwf_ctx* ctx, const void* U, int canon_prec, void* stream) {
     return fail(QDWF_EINVAL, "canon_prec must be QDWF_F64 or QDWF_F32");
   DeviceGuard dg(ctx->device);
   TRY(launch_pack_links(ctx, U, canon_prec, S(stream)));
+  TRY(launch_doubled_links(ctx, S(stream)));
   ctx->gauge_set = true;
   return QDWF_OK;
 }

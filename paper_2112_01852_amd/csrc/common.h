@@ -106,6 +106,7 @@ struct HopShape {
   int nrb;       // right-hand sides per block
   int xcd;       // 1: XCD-aware block order
   int lds_pad;   // extra LDS bytes per block: caps the blocks resident per CU
+  int sweep;     // 1: the t-sweep traversal of the full operator where it applies
 };
 
 }  // namespace qdwf
@@ -119,6 +120,10 @@ struct qdwf_ctx {
   int tile[4];             // tile of the traversal order (1 on the sweep dimension)
   int order[2];            // split and sweep dimension of the traversal order
   void* d_links[4];        // per precision: [2][4][Vh][18] reals, bc folded in
+  void* d_dlinks[4];       // per precision (32- and 16-bit, t-sweep geometries only):
+                           // [2][Vh][8][18], the 8 links of each site (U_mu(x), then
+                           // U_mu(x - mu) taken from the other parity), bc folded in
+  int32_t* d_idx;          // [V] internal index of each lex site
   bool gauge_set;
   double* d_mat64;         // [MAT_COUNT][2][Ls][Ls]
   float* d_mat32;
@@ -154,6 +159,18 @@ struct HopArgs {
 };
 int launch_hop(qdwf_ctx* ctx, int prec, int layout, int dagger, const HopArgs& a,
                hipStream_t st, const HopShape* shape = nullptr);
+
+// t-sweep traversal of the full operator (both parities, epi, z = the input
+// itself, no fused M_ee^-1, the context's links): Ls = 16, interleaved
+// layout, 32- or 16-bit storage, Lx in {8, 16, 24, 32}. sweep_eligible says
+// whether launch_sweep accepts the call; launch_hop routes there when the
+// launch shape asks for it (HopShape::sweep) or QDWF_SWEEP=1 forces it.
+bool sweep_eligible(const qdwf_ctx* ctx, int prec, int layout, const HopArgs& a);
+int launch_sweep(qdwf_ctx* ctx, int prec, int dagger, const HopArgs& a, hipStream_t st);
+// Whether the context keeps doubled links for the t-sweep, and their build
+// from the packed links (after every gauge update).
+bool sweep_geometry(const qdwf::Geom& g);
+int launch_doubled_links(qdwf_ctx* ctx, hipStream_t st);
 
 // Wilson family (no fifth-dimension terms, links read from global memory):
 // out = hop_scale * D_h in  (+ alpha z when epi), D_h^dag when dagger, with

@@ -22,6 +22,7 @@
 #include <cstdlib>
 
 #include "common.h"
+#include "hopcore.h"
 #include "siteio.h"
 #include "spin.h"
 
@@ -42,85 +43,6 @@ struct HopK {
   double c_over_b, mf, hop_scale_b, alpha, beta;
   double rpow[4];      // (-beta/alpha)^(2^j), j < 4: the M_ee^-1 scan
 };
-
-__device__ inline int xcd_remap(int bid, int nb) {
-  // hardware hands block i to XCD i % 8; give XCD x a contiguous range instead
-  const int per = nb >> 3, rem = nb & 7;
-  const int x = bid & 7, k = bid >> 3;
-  return (x < rem) ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
-}
-
-// Link staging stride in LDS (reals per link): 16-byte aligned rows.
-template <class T> struct LinkStride { static constexpr int v = 20; };
-template <> struct LinkStride<double> { static constexpr int v = 18; };
-
-template <class T>
-__device__ inline void load_link(const T* __restrict__ p, T* U) {
-  if constexpr (sizeof(T) == 4) {
-    const float4* q = reinterpret_cast<const float4*>(p);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const float4 w = q[k];
-      U[4 * k] = w.x; U[4 * k + 1] = w.y; U[4 * k + 2] = w.z; U[4 * k + 3] = w.w;
-    }
-    const float2 w = *reinterpret_cast<const float2*>(p + 16);
-    U[16] = w.x; U[17] = w.y;
-  } else {
-    const double2* q = reinterpret_cast<const double2*>(p);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const double2 w = q[k];
-      U[2 * k] = w.x; U[2 * k + 1] = w.y;
-    }
-  }
-}
-
-
-// s +- 1 exchange inside a group of Ls lanes. fm(c, x, a) = a + c x(s-1) and
-// fp(c, x, a) = a + c x(s+1), cyclically in s (the walls are handled by the
-// caller's coefficients). Generic Ls uses cross-lane permutes.
-template <bool DPP16> struct SShift {
-  int src_m, src_p;
-  template <class T> __device__ inline T fm(T c, T x, T a) const { return fmac(c, (T)__shfl(x, src_m, 64), a); }
-  template <class T> __device__ inline T fp(T c, T x, T a) const { return fmac(c, (T)__shfl(x, src_p, 64), a); }
-};
-
-// Ls = 16: a group is one DPP row and the exchange is a row rotate. In FP32
-// the rotate is the source modifier of the FMA itself (one instruction); the
-// s_nop covers the two wait states a DPP read needs after a VALU write of the
-// same register, which the compiler does not track through inline assembly.
-// FP64 has no row rotate on 64-bit operands, so each half is moved first.
-template <int R> __device__ inline int dpp_ror(int v) {
-  return __builtin_amdgcn_mov_dpp(v, 0x120 + R, 0xF, 0xF, false);
-}
-// v_fmac_f32 with its first source read through a DPP row rotate by R lanes
-#define QDWF_FMAC_ROR(R)                                                              \
-  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_ror:" #R " row_mask:0xf bank_mask:0xf" \
-      : "+v"(a) : "v"(x), "v"(c))
-template <> struct SShift<true> {
-  int src_m, src_p;
-  // a + c x(lane - R), R = 1..15, within the 16-lane row
-  template <int R> __device__ inline float fr(float c, float x, float a) const {
-    static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 12 || R == 14 || R == 15,
-                  "rotation not instantiated");
-    if constexpr (R == 1) QDWF_FMAC_ROR(1);
-    else if constexpr (R == 2) QDWF_FMAC_ROR(2);
-    else if constexpr (R == 4) QDWF_FMAC_ROR(4);
-    else if constexpr (R == 8) QDWF_FMAC_ROR(8);
-    else if constexpr (R == 12) QDWF_FMAC_ROR(12);
-    else if constexpr (R == 14) QDWF_FMAC_ROR(14);
-    else QDWF_FMAC_ROR(15);
-    return a;
-  }
-  template <int R> __device__ inline double fr(double c, double x, double a) const {
-    const long long b = __double_as_longlong(x);
-    const int lo = dpp_ror<R>((int)b), hi = dpp_ror<R>((int)(b >> 32));
-    return fmac(c, __longlong_as_double(((long long)hi << 32) | (unsigned int)lo), a);
-  }
-  template <class T> __device__ inline T fm(T c, T x, T a) const { return fr<1>(c, x, a); }
-  template <class T> __device__ inline T fp(T c, T x, T a) const { return fr<15>(c, x, a); }
-};
-#undef QDWF_FMAC_ROR
 
 // Target occupancy (waves per SIMD) the register allocator plans for: two for
 // 32- and 64-bit storage, whose arithmetic needs the registers to keep two
@@ -377,6 +299,11 @@ HopShape default_shape(const qdwf_ctx* ctx, int prec, int nrhs) {
   // several right-hand sides of a block (the tuner still tries both)
   sh.nrb = 1;
   sh.lds_pad = 0;
+  // the t-sweep of the full operator: measured faster than the checkerboard
+  // traversal with 16- and 32-wide rows (one and two blocks of 8 waves per
+  // CU), slower with 24-wide ones (6 waves per CU); the tuner tries it for
+  // every row width it takes
+  sh.sweep = (ctx->g.L[0] == 16 || ctx->g.L[0] == 32) ? 1 : 0;
   if (const char* e = std::getenv("QDWF_HOP_LDS_PAD")) sh.lds_pad = std::atoi(e);
   if (const char* e = std::getenv("QDWF_HOP_THREADS")) {
     const int t = std::atoi(e);
@@ -395,6 +322,11 @@ int launch_hop(qdwf_ctx* ctx, int prec, int layout, int dagger, const HopArgs& a
   const int G = (sh.threads / 64) * (64 / ctx->g.Ls);
   if (sh.threads % 64 || sh.threads < 64 || sh.threads > 256 || sh.nrb < 1 || G % sh.nrb)
     return fail(QDWF_EINVAL, "invalid hop launch shape (threads %d, nrb %d)", sh.threads, sh.nrb);
+  // the full operator on one whole field takes the t-sweep where it applies
+  // (QDWF_SWEEP=1 / 0 forces it on / off where it applies)
+  const char* force = std::getenv("QDWF_SWEEP");
+  const bool sweep = (force && *force) ? force[0] == '1' : sh.sweep != 0;
+  if (sweep && sweep_eligible(ctx, prec, layout, a)) return launch_sweep(ctx, prec, dagger, a, st);
   auto go = [&](auto tag_s) -> int {
     typedef decltype(tag_s) S;
     if (layout == QDWF_RIRI) {

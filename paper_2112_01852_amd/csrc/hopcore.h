@@ -1,0 +1,91 @@
+// Pieces of the Domain Wall kernel shared by its two traversals (one lane
+// per 5D site in checkerboard order, and the t-sweep of whole x-rows): the
+// XCD-aware block renumbering, link loads into registers, and the s +- 1
+// exchange between the slices of a site held by neighbouring lanes.
+#pragma once
+
+#include "common.h"
+#include "spin.h"
+
+namespace qdwf {
+
+__device__ inline int xcd_remap(int bid, int nb) {
+  // hardware hands block i to XCD i % 8; give XCD x a contiguous range instead
+  const int per = nb >> 3, rem = nb & 7;
+  const int x = bid & 7, k = bid >> 3;
+  return (x < rem) ? x * (per + 1) + k : rem * (per + 1) + (x - rem) * per + k;
+}
+
+// Link staging stride in LDS (reals per link): 16-byte aligned rows.
+template <class T> struct LinkStride { static constexpr int v = 20; };
+template <> struct LinkStride<double> { static constexpr int v = 18; };
+
+template <class T>
+__device__ inline void load_link(const T* __restrict__ p, T* U) {
+  if constexpr (sizeof(T) == 4) {
+    const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float4 w = q[k];
+      U[4 * k] = w.x; U[4 * k + 1] = w.y; U[4 * k + 2] = w.z; U[4 * k + 3] = w.w;
+    }
+    const float2 w = *reinterpret_cast<const float2*>(p + 16);
+    U[16] = w.x; U[17] = w.y;
+  } else {
+    const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double2 w = q[k];
+      U[2 * k] = w.x; U[2 * k + 1] = w.y;
+    }
+  }
+}
+
+
+// s +- 1 exchange inside a group of Ls lanes. fm(c, x, a) = a + c x(s-1) and
+// fp(c, x, a) = a + c x(s+1), cyclically in s (the walls are handled by the
+// caller's coefficients). Generic Ls uses cross-lane permutes.
+template <bool DPP16> struct SShift {
+  int src_m, src_p;
+  template <class T> __device__ inline T fm(T c, T x, T a) const { return fmac(c, (T)__shfl(x, src_m, 64), a); }
+  template <class T> __device__ inline T fp(T c, T x, T a) const { return fmac(c, (T)__shfl(x, src_p, 64), a); }
+};
+
+// Ls = 16: a group is one DPP row and the exchange is a row rotate. In FP32
+// the rotate is the source modifier of the FMA itself (one instruction); the
+// s_nop covers the two wait states a DPP read needs after a VALU write of the
+// same register, which the compiler does not track through inline assembly.
+// FP64 has no row rotate on 64-bit operands, so each half is moved first.
+template <int R> __device__ inline int dpp_ror(int v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x120 + R, 0xF, 0xF, false);
+}
+// v_fmac_f32 with its first source read through a DPP row rotate by R lanes
+#define QDWF_FMAC_ROR(R)                                                              \
+  asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_ror:" #R " row_mask:0xf bank_mask:0xf" \
+      : "+v"(a) : "v"(x), "v"(c))
+template <> struct SShift<true> {
+  int src_m, src_p;
+  // a + c x(lane - R), R = 1..15, within the 16-lane row
+  template <int R> __device__ inline float fr(float c, float x, float a) const {
+    static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 12 || R == 14 || R == 15,
+                  "rotation not instantiated");
+    if constexpr (R == 1) QDWF_FMAC_ROR(1);
+    else if constexpr (R == 2) QDWF_FMAC_ROR(2);
+    else if constexpr (R == 4) QDWF_FMAC_ROR(4);
+    else if constexpr (R == 8) QDWF_FMAC_ROR(8);
+    else if constexpr (R == 12) QDWF_FMAC_ROR(12);
+    else if constexpr (R == 14) QDWF_FMAC_ROR(14);
+    else QDWF_FMAC_ROR(15);
+    return a;
+  }
+  template <int R> __device__ inline double fr(double c, double x, double a) const {
+    const long long b = __double_as_longlong(x);
+    const int lo = dpp_ror<R>((int)b), hi = dpp_ror<R>((int)(b >> 32));
+    return fmac(c, __longlong_as_double(((long long)hi << 32) | (unsigned int)lo), a);
+  }
+  template <class T> __device__ inline T fm(T c, T x, T a) const { return fr<1>(c, x, a); }
+  template <class T> __device__ inline T fp(T c, T x, T a) const { return fr<15>(c, x, a); }
+};
+#undef QDWF_FMAC_ROR
+
+}  // namespace qdwf

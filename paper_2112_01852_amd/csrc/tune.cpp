@@ -52,8 +52,8 @@ void cache_store(const std::string& key, const HopShape& s, double ms) {
   if (!path || !*path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"nrb\": %d, \"xcd\": %d, \"lds_pad\": %d, \"ms\": %.6f}\n",
-               key.c_str(), s.threads, s.nrb, s.xcd, s.lds_pad, ms);
+  std::fprintf(f, "{\"key\": \"%s\", \"threads\": %d, \"nrb\": %d, \"xcd\": %d, \"lds_pad\": %d, \"sweep\": %d, \"ms\": %.6f}\n",
+               key.c_str(), s.threads, s.nrb, s.xcd, s.lds_pad, s.sweep, ms);
   std::fclose(f);
 }
 
@@ -68,8 +68,8 @@ bool cache_load(const std::string& key, HopShape* out) {
     char k[256];
     HopShape s;
     double ms;
-    if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"threads\": %d, \"nrb\": %d, \"xcd\": %d, \"lds_pad\": %d, \"ms\": %lf}",
-                    k, &s.threads, &s.nrb, &s.xcd, &s.lds_pad, &ms) == 6 &&
+    if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"threads\": %d, \"nrb\": %d, \"xcd\": %d, \"lds_pad\": %d, \"sweep\": %d, \"ms\": %lf}",
+                    k, &s.threads, &s.nrb, &s.xcd, &s.lds_pad, &s.sweep, &ms) == 7 &&
         key == k) {
       *out = s;   // the last entry for a key wins
       found = true;
@@ -168,7 +168,7 @@ int qdwf_tune(qdwf_ctx* ctx, int prec, int layout, int nrhs, void* ws, void* str
         if (G % nrb || nrb > nrhs || (nrb > 1 && G / nrb < 2)) continue;
         for (int xcd = 0; xcd < 2; ++xcd)
           for (int pad : {0, 24 * 1024, 44 * 1024}) {
-            HopShape s = {64 * waves, nrb, xcd, pad};
+            HopShape s = {64 * waves, nrb, xcd, pad, 0};
             // warm-up launch; shapes the kernel rejects (LDS) are skipped
             if (launch_hop(ctx, prec, layout, dagger, a, st, &s) != QDWF_OK) continue;
             QDWF_HIP(hipEventRecord(e0, st));
@@ -182,6 +182,25 @@ int qdwf_tune(qdwf_ctx* ctx, int prec, int layout, int nrhs, void* ws, void* str
               best = s;
             }
           }
+      }
+    }
+    // the t-sweep serves the full operator wherever it applies; keep it when
+    // it beats the best checkerboard shape (the other fields still serve
+    // the launches it does not take)
+    if (sweep_eligible(ctx, prec, layout, a)) {
+      HopShape s = best;
+      s.sweep = 1;
+      if (launch_hop(ctx, prec, layout, dagger, a, st, &s) == QDWF_OK) {
+        QDWF_HIP(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) launch_hop(ctx, prec, layout, dagger, a, st, &s);
+        QDWF_HIP(hipEventRecord(e1, st));
+        QDWF_HIP(hipEventSynchronize(e1));
+        float ms = 0;
+        QDWF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (ms / reps < best_t) {
+          best_t = ms / reps;
+          best = s;
+        }
       }
     }
     {
