@@ -92,6 +92,71 @@ template <> struct StoreNT<_Float16> : StoreNT16<_Float16> {};
 template <> struct StoreNT<bf16> : StoreNT16<bf16> {};
 constexpr int LSTR = 20;    // reals per staged link (16-byte rows)
 
+// One hop direction D of a lane's 5D site, accumulated into acc: the
+// neighbour spinor src (raw psi), for D (not D^dag) first multiplied by
+// A / b = 1 + (c/b) C with the s +- 1 values from the neighbouring lanes of the
+// DPP row; projected to a half spinor, multiplied by the link at lks + D *
+// LSTR (U_mu(x) forward, U_mu(x - mu)^dag backward) and reconstructed.
+// refill() runs once src has been read, so a buffer may be reloaded there.
+template <bool DAG, int D, bool FIRST, class Refill>
+__device__ inline __attribute__((always_inline)) void dir_acc(
+    const SShift<true>& sh, float cm, float cp, const float* lks, const float* src, float* acc,
+    Refill refill) {
+  constexpr int MU = D & 3;
+  constexpr bool FWD = D < 4;
+  // (1 - g) on forward hops and (1 + g) on backward ones; swapped for D^dag
+  constexpr int SG = (FWD != DAG) ? -1 : +1;
+  float v[24];
+  if constexpr (!DAG) {
+    // chi / b = psi + (c/b) (P+ psi_{s-1} + P- psi_{s+1}), walls included
+#pragma unroll
+    for (int i = 0; i < 12; ++i) v[i] = sh.fm(cm, src[i], src[i]);
+#pragma unroll
+    for (int i = 12; i < 24; ++i) v[i] = sh.fp(cp, src[i], src[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 24; ++i) v[i] = src[i];
+  }
+  refill();
+  float h[12], uh[12], U[18];
+  load_link(lks + D * LSTR, U);
+  project<MU, SG>(v, h);
+  su3_mul<!FWD>(U, h, uh);
+  recon_acc<MU, SG, FIRST>(uh, acc);
+}
+
+// The 5D end of the full operator on the accumulated hop h (acc) of a lane:
+// for D^dag first h <- A^dag h / b; then out = hop_scale b h + alpha psi +
+// beta C psi (C^dag for D^dag), psi the lane's own site.
+template <bool DAG>
+__device__ inline __attribute__((always_inline)) void epilogue(
+    const SShift<true>& sh, float cm, float cp, float hs, float al, float bm, float bp,
+    const float* psi, float* acc) {
+  if constexpr (DAG) {
+    // A^dag h / b = h + (c/b) C^dag h: upper spins from s+1, lower from s-1
+    float tmp[24];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) tmp[i] = sh.fp(cp, acc[i], acc[i]);
+#pragma unroll
+    for (int i = 12; i < 24; ++i) tmp[i] = sh.fm(cm, acc[i], acc[i]);
+#pragma unroll
+    for (int i = 0; i < 24; ++i) acc[i] = tmp[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 24; ++i) acc[i] = fmac(al, psi[i], hs * acc[i]);
+  if constexpr (!DAG) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc[i] = sh.fm(bm, psi[i], acc[i]);
+#pragma unroll
+    for (int i = 12; i < 24; ++i) acc[i] = sh.fp(bp, psi[i], acc[i]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc[i] = sh.fp(bp, psi[i], acc[i]);
+#pragma unroll
+    for (int i = 12; i < 24; ++i) acc[i] = sh.fm(bm, psi[i], acc[i]);
+  }
+}
+
 template <class S, bool DAG, int W>
 __global__ void __launch_bounds__(W * 16) __attribute__((amdgpu_waves_per_eu(2, 2)))
 sweep_kernel(SweepK k) {
@@ -236,32 +301,8 @@ sweep_kernel(SweepK k) {
 
     const float* lks = Lk[t & 1] + x * 8 * LSTR;
     float acc[24];
-    // direction D from the spinor src; refill() runs once src is no longer
-    // needed (the buffer it reloads is read before it)
     auto dir = [&](auto Dc, auto Fc, const float* src, auto refill) __attribute__((always_inline)) {
-      constexpr int D = decltype(Dc)::value;
-      constexpr bool FIRST = decltype(Fc)::value;
-      constexpr int MU = D & 3;
-      constexpr bool FWD = D < 4;
-      // (1 - g) on forward hops and (1 + g) on backward ones; swapped for D^dag
-      constexpr int SG = (FWD != DAG) ? -1 : +1;
-      float v[24];
-      if constexpr (!DAG) {
-        // chi / b = psi + (c/b) (P+ psi_{s-1} + P- psi_{s+1}), walls included
-#pragma unroll
-        for (int i = 0; i < 12; ++i) v[i] = sh.fm(cm, src[i], src[i]);
-#pragma unroll
-        for (int i = 12; i < 24; ++i) v[i] = sh.fp(cp, src[i], src[i]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 24; ++i) v[i] = src[i];
-      }
-      refill();
-      float h[12], uh[12], U[18];
-      load_link(lks + D * LSTR, U);
-      project<MU, SG>(v, h);
-      su3_mul<!FWD>(U, h, uh);
-      recon_acc<MU, SG, FIRST>(uh, acc);
+      dir_acc<DAG, decltype(Dc)::value, decltype(Fc)::value>(sh, cm, cp, lks, src, acc, refill);
     };
     auto none = [] {};
     {
@@ -287,36 +328,11 @@ sweep_kernel(SweepK k) {
     dir(IC<6>(), std::false_type(), va, none);                               // -z
     dir(IC<3>(), std::false_type(), R, [&] { put(t + 1, R); });             // +t
 
-    if constexpr (DAG) {
-      // A^dag h / b = h + (c/b) C^dag h: upper spins from s+1, lower from s-1
-      float tmp[24];
-#pragma unroll
-      for (int i = 0; i < 12; ++i) tmp[i] = sh.fp(cp, acc[i], acc[i]);
-#pragma unroll
-      for (int i = 12; i < 24; ++i) tmp[i] = sh.fm(cm, acc[i], acc[i]);
-#pragma unroll
-      for (int i = 0; i < 24; ++i) acc[i] = tmp[i];
-    }
-    // out = hop_scale b h + alpha psi + beta C psi (C^dag for D^dag), psi the
-    // own site, read back from the lane's exchange slot
     {
+      // psi of the own site, read back from the lane's exchange slot
       float z0[24];
       get(t, x, z0);
-      const float hs = k.hsb, al = k.alpha;
-      const float bm = k.beta * wm, bp = k.beta * wp;
-#pragma unroll
-      for (int i = 0; i < 24; ++i) acc[i] = fmac(al, z0[i], hs * acc[i]);
-      if constexpr (!DAG) {
-#pragma unroll
-        for (int i = 0; i < 12; ++i) acc[i] = sh.fm(bm, z0[i], acc[i]);
-#pragma unroll
-        for (int i = 12; i < 24; ++i) acc[i] = sh.fp(bp, z0[i], acc[i]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 12; ++i) acc[i] = sh.fp(bp, z0[i], acc[i]);
-#pragma unroll
-        for (int i = 12; i < 24; ++i) acc[i] = sh.fm(bm, z0[i], acc[i]);
-      }
+      epilogue<DAG>(sh, cm, cp, k.hsb, k.alpha, k.beta * wm, k.beta * wp, z0, acc);
     }
     store_nt(O + p * k.half, c0, acc);
     c0 = c1; c1 = c2;
