@@ -300,16 +300,15 @@ HopShape default_shape(const qdwf_ctx* ctx, int prec, int nrhs) {
   sh.nrb = 1;
   sh.lds_pad = 0;
   // the t-sweep of the full operator: measured faster than the checkerboard
-  // traversal with 16- and 32-wide rows (one and two blocks of 8 waves per
-  // CU), slower with 24-wide ones (6 waves per CU); the tuner tries it for
-  // every row width it takes
-  sh.sweep = (ctx->g.L[0] == 16 || ctx->g.L[0] == 32) ? 1 : 0;
+  // traversal in FP32 with 16- and 32-wide rows (one and two blocks of 8
+  // waves per CU); slower with 24-wide ones (6 waves per CU) and with 16-bit
+  // storage; the tuner tries it wherever it applies
+  sh.sweep = (prec == QDWF_F32 && (ctx->g.L[0] == 16 || ctx->g.L[0] == 32)) ? 1 : 0;
   if (const char* e = std::getenv("QDWF_HOP_LDS_PAD")) sh.lds_pad = std::atoi(e);
   if (const char* e = std::getenv("QDWF_HOP_THREADS")) {
     const int t = std::atoi(e);
     if (t >= 64 && t <= 256 && t % 64 == 0) sh.threads = t;
   }
-  (void)prec;
   (void)nrhs;
   return sh;
 }
