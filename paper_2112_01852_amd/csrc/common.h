@@ -124,6 +124,8 @@ struct qdwf_ctx {
                            // [2][Vh][8][18], the 8 links of each site (U_mu(x), then
                            // U_mu(x - mu) taken from the other parity), bc folded in
   int32_t* d_idx;          // [V] internal index of each lex site
+  void* d_wlinks[4];       // FP64 and FP32, Ls = 1 only: lane-major links of the Wilson
+                           // kernel, per [parity][direction]: [4][Vh][4] then [Vh][2] reals
   bool gauge_set;
   double* d_mat64;         // [MAT_COUNT][2][Ls][Ls]
   float* d_mat32;
@@ -171,6 +173,8 @@ int launch_sweep(qdwf_ctx* ctx, int prec, int dagger, const HopArgs& a, hipStrea
 // from the packed links (after every gauge update).
 bool sweep_geometry(const qdwf::Geom& g);
 int launch_doubled_links(qdwf_ctx* ctx, hipStream_t st);
+// Lane-major links of the Wilson kernel (Ls = 1 contexts), after every gauge update.
+int launch_wilson_links(qdwf_ctx* ctx, hipStream_t st);
 
 // Wilson family (no fifth-dimension terms, links read from global memory):
 // out = hop_scale * D_h in  (+ alpha z when epi), D_h^dag when dagger, with

@@ -100,6 +100,25 @@ def test_multi_rhs_columns(q):
     D.close()
 
 
+def test_gauge_update_reaches_lane_major_links(q):
+    """4D contexts read lane-major copies of the links, rebuilt by every
+    qdwf_set_gauge: a second gauge field must replace the first."""
+    L = (8, 4, 4, 6)
+    a = cpu.Action(L=L, Ls=1, **SHAMIR)
+    psi = I.gaussian_spinor(L, 1, 741)
+    D = q.Dirac(L, 1, **SHAMIR)
+    for seed in (742, 743):
+        U = I.gauge_field(L, "haar", seed)
+        D.set_gauge(U)
+        for prec in (0, 1, 3):
+            f = D.pack(psi, prec, q.QDWF_RIRI, q.QDWF_FULL)
+            out = D.field(prec, q.QDWF_FULL)
+            q.qdwf_apply_Dw(D.ctx, out, f, 0.1, 1, prec, q.QDWF_RIRI)
+            got = D.unpack(out, prec, q.QDWF_RIRI, q.QDWF_FULL).cpu().numpy()
+            assert _rel(got, cpu.wilson(a, U, psi, 0.1, dagger=True)) < TOL[prec]
+    D.close()
+
+
 def test_invalid_arguments(q):
     D = q.Dirac((4, 4, 4, 4), 1, **SHAMIR)
     D.set_gauge(I.gauge_field((4, 4, 4, 4), "haar", 730))
