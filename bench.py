@@ -226,7 +226,7 @@ def wilson_shapes_bench(args, torch, q, I):
             fout = D.field(prec, q.QDWF_FULL, zero=False)
             steps = max(args.steps // 2, 5)
             ms = time_launches(lambda: q.qdwf_apply_Dh(D.ctx, fout, fin, q.QDWF_FULL, 0, prec,
-                                                       q.QDWF_RIRI), steps, 3, torch)
+                                                       q.QDWF_RIRI), steps, 3, torch, ramp_s=0.2)
             half_in, half_out = fin[: fin.numel() // 2], fout[: fout.numel() // 2]
             ms_eo = time_launches(lambda: q.qdwf_apply_Dh(D.ctx, half_out, half_in, q.QDWF_ODD, 0,
                                                           prec, q.QDWF_RIRI), steps, 3, torch)
@@ -506,7 +506,7 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.9,
                     help="offered load relative to one-at-a-time plain FP64 service")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
-    ap.add_argument("--only", choices=["solver"], default=None,
+    ap.add_argument("--only", choices=["solver", "wilson"], default=None,
                     help="run only this row and print its JSON object (for profiling)")
     ap.add_argument("--inner", default="",
                     help="comma list of solver inner precisions (f64,f32,f16,bf16; default all)")
@@ -523,6 +523,11 @@ def main():
     q.lib()
     if args.only == "solver":
         print(json.dumps({"solver_24x24x24x24x16": solver_bench(args, torch, q, I)}), flush=True)
+        return
+    if args.only == "wilson":
+        probe = copy_probe(torch)   # also the counters' calibration copy
+        print(json.dumps({"attainable_hbm": probe,
+                          "paper_wilson_shapes": wilson_shapes_bench(args, torch, q, I)}), flush=True)
         return
     probe = copy_probe(torch)
     log("copy probe", probe)

@@ -147,8 +147,8 @@ const char* qdwf_last_error(void);
  * Ls = 16 and Lx in {8, 16, 24, 32} it also allocates doubled links (the 8
  * links of each site, 2 x 144 x V/2 reals) in FP32, FP16 and BF16 for the
  * t-sweep form of qdwf_apply_D: 1.2 GB at 32^4. With Ls = 1 it allocates
- * lane-major links for the Wilson kernel instead (2 x 8 x 18 x V/2 reals in
- * FP64 and in FP32). Distinct contexts are independent; one context must not
+ * lane-major forward links for the Wilson kernel instead (2 x 4 x 18 x V/2
+ * reals in FP64 and in FP32). Distinct contexts are independent; one context must not
  * be used from two threads at once. */
 int qdwf_create(const qdwf_action* act, int device, qdwf_ctx** out);
 int qdwf_destroy(qdwf_ctx* ctx);

@@ -244,7 +244,7 @@ int qdwf_create(const qdwf_action* act, int device, qdwf_ctx** out) {
       e = hipMalloc(&c->d_dlinks[p], 2 * link_reals * prec_bytes(p));
   if (g.Ls == 1)   // FP64 and FP32: measured slower with 16-bit storage
     for (int p = QDWF_F64; p <= QDWF_F32 && e == hipSuccess; ++p)
-      e = hipMalloc(&c->d_wlinks[p], (size_t)2 * 8 * 18 * g.Vh * prec_bytes(p));
+      e = hipMalloc(&c->d_wlinks[p], (size_t)2 * 4 * 18 * g.Vh * prec_bytes(p));
   if (e == hipSuccess)
     e = hipMemcpy(c->d_nbr, c->h_nbr.data(), sizeof(int32_t) * c->h_nbr.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)

@@ -124,8 +124,8 @@ struct qdwf_ctx {
                            // [2][Vh][8][18], the 8 links of each site (U_mu(x), then
                            // U_mu(x - mu) taken from the other parity), bc folded in
   int32_t* d_idx;          // [V] internal index of each lex site
-  void* d_wlinks[4];       // FP64 and FP32, Ls = 1 only: lane-major links of the Wilson
-                           // kernel, per [parity][direction]: [4][Vh][4] then [Vh][2] reals
+  void* d_wlinks[4];       // FP64 and FP32, Ls = 1 only: lane-major forward links of the
+                           // Wilson kernel, per [parity][mu]: [4][Vh][4] then [Vh][2] reals
   bool gauge_set;
   double* d_mat64;         // [MAT_COUNT][2][Ls][Ls]
   float* d_mat32;

@@ -7,11 +7,10 @@
 // reuse of links across the fifth dimension to exploit at Ls = 1, so each lane
 // reads its 8 links straight from global memory and there is no LDS stage and
 // no barrier. With Ls = 1 the links come from a lane-major copy built by
-// qdwf_set_gauge: the 8 links of every site (U_mu(x), then U_mu(x - mu)) cut
-// into chunks stored chunk-major over the sites, so that one load
-// instruction of a wavefront reads consecutive words (5 loads per link
-// instead of 9 narrow, strided ones): 25-35 % faster in FP64, about 4 % in
-// FP32; 16-bit storage keeps the packed links (no gain measured there). With Ls > 1 the slices of a site
+// qdwf_set_gauge: the 4 forward links of every site cut into chunks stored
+// chunk-major over the sites, so that one load instruction of a wavefront
+// reads consecutive words (5 loads per link instead of 9 narrow, strided
+// ones); a backward link is read as its neighbour's forward link. With Ls > 1 the slices of a site
 // share its links and the packed [parity][mu][site] links are read.
 #include "common.h"
 #include "siteio.h"
@@ -21,14 +20,15 @@ namespace qdwf {
 
 namespace {
 
-// Lane-major links of Ls = 1 contexts: for each parity and direction 0..7,
+// Lane-major links of Ls = 1 contexts: for each parity and direction mu,
 // four chunks of 4 reals, each chunk-major over the sites ([c][site][4]),
 // then the last 2 reals of every link ([site][2]): 18 reals per link, no
-// padding, and consecutive lanes read consecutive words.
+// padding, and consecutive lanes read consecutive words. Forward links only:
+// the backward link U_mu(x - mu) is the forward link of the neighbour.
 template <class S> struct WLinkIO {
   typedef typename Store<S>::compute T;
-  __device__ static inline void load(const S* __restrict__ w, int p, int d, int i, int Vh, T* U) {
-    const S* base = w + ((long)p * 8 + d) * Vh * 18;
+  __device__ static inline void load(const S* __restrict__ w, int p, int mu, int i, int Vh, T* U) {
+    const S* base = w + ((long)p * 4 + mu) * Vh * 18;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const S* q = base + ((long)c * Vh + i) * 4;
@@ -103,7 +103,8 @@ __global__ void __launch_bounds__(256) wilson_kernel(WilK k) {
     T v[24], U[18], h[12], uh[12];
     SiteIO<S, LAYOUT>::load(in, n, s, k.Ls, k.plane, v);
     if constexpr (WL) {
-      WLinkIO<S>::load(reinterpret_cast<const S*>(k.wl), p, D, i, Vh, U);
+      // forward: U_mu(x) of this site; backward: U_mu(x - mu) of the neighbour
+      WLinkIO<S>::load(reinterpret_cast<const S*>(k.wl), FWD ? p : q, MU, FWD ? i : n, Vh, U);
     } else {
       // forward: U_mu(x) of this site; backward: U_mu(x - mu) of the neighbour
       const long li = FWD ? (((long)p * 4 + MU) * Vh + i) : (((long)q * 4 + MU) * Vh + n);
@@ -158,19 +159,14 @@ int run_wilson(qdwf_ctx* ctx, int prec, const HopArgs& a, hipStream_t st) {
 }
 
 template <class S>
-__global__ void wlink_kernel(const S* __restrict__ links, S* __restrict__ wl,
-                             const int* __restrict__ nbr, int Vh) {
-  const long total = 2L * 8 * Vh;
+__global__ void wlink_kernel(const S* __restrict__ links, S* __restrict__ wl, int Vh) {
+  const long total = 2L * 4 * Vh;
   for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
        t += (long)gridDim.x * blockDim.x) {
     const int i = (int)(t % Vh);
-    const int d = (int)((t / Vh) % 8);
-    const int p = (int)(t / (8L * Vh));
-    const int mu = d & 3;
-    // forward: U_mu(x) at x; backward: U_mu(x - mu), stored at x - mu (other parity)
-    const S* src = d < 4 ? links + (((long)p * 4 + mu) * Vh + i) * 18
-                         : links + (((long)(1 - p) * 4 + mu) * Vh + nbr[((long)p * 8 + d) * Vh + i]) * 18;
-    S* base = wl + ((long)p * 8 + d) * Vh * 18;
+    const long pm = t / Vh;   // parity * 4 + mu, as in the packed links
+    const S* src = links + t * 18;
+    S* base = wl + pm * Vh * 18;
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -184,14 +180,14 @@ __global__ void wlink_kernel(const S* __restrict__ links, S* __restrict__ wl,
 
 int launch_wilson_links(qdwf_ctx* ctx, hipStream_t st) {
   const Geom& g = ctx->g;
-  const long total = 2L * 8 * g.Vh;
+  const long total = 2L * 4 * g.Vh;
   long blocks = (total + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   auto go = [&](auto tag, int p) {
     typedef decltype(tag) S;
     hipLaunchKernelGGL(wlink_kernel<S>, dim3((unsigned)blocks), dim3(256), 0, st,
                        reinterpret_cast<const S*>(ctx->d_links[p]),
-                       reinterpret_cast<S*>(ctx->d_wlinks[p]), ctx->d_nbr, g.Vh);
+                       reinterpret_cast<S*>(ctx->d_wlinks[p]), g.Vh);
   };
   for (int p = QDWF_F64; p <= QDWF_BF16; ++p) {
     if (!ctx->d_wlinks[p]) continue;
