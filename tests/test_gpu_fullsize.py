@@ -1,9 +1,10 @@
 """The benchmark workload itself: Mobius D and D^dag on the full 32^4 x 16
 lattice, with the benchmark's inputs (Haar links seed 2000, Gaussian spinor
 seed 2001, drawn in single precision as the benchmark draws them) and the
-launch configuration it times (default shape, RIRI), read back on sampled 5D
-sites and compared with the FP64 oracle evaluated site by site on the same
-inputs widened to FP64.
+launch configuration it times (default shape, RIRI: the t-sweep for FP32),
+with the checkerboard kernel and the FP16 t-sweep forced as extra cases,
+read back on sampled 5D sites and compared with the FP64 oracle evaluated
+site by site on the same inputs widened to FP64.
 
 Sampled sites: every combination of the lattice edges (coordinate 0 and
 L - 1 in each direction, slices 0 and Ls - 1, where the boundary phase and
@@ -56,9 +57,15 @@ def full():
     D.close()
 
 
-@pytest.mark.parametrize("prec,dagger", [(1, 0), (1, 1), (0, 0), (2, 0)])
-def test_full_lattice_sampled_sites(full, prec, dagger):
+@pytest.mark.parametrize("prec,dagger,form", [(1, 0, ""), (1, 1, ""), (1, 0, "0"), (1, 1, "0"),
+                                              (0, 0, ""), (2, 0, ""), (2, 0, "1")])
+def test_full_lattice_sampled_sites(full, prec, dagger, form, monkeypatch):
+    """form: "" the library's default (the t-sweep for FP32 at this size, the
+    checkerboard kernel otherwise), "0" / "1" the checkerboard kernel / the
+    t-sweep forced."""
     q, torch, a, U, psi, psi_d, D, idx = full
+    if form:
+        monkeypatch.setenv("QDWF_SWEEP", form)
     fin = D.field(prec, q.QDWF_FULL, zero=False)
     q.qdwf_pack_spinor(D.ctx, fin, prec, q.QDWF_RIRI, psi_d, q.QDWF_FULL)
     fout = D.field(prec, q.QDWF_FULL, zero=False)
