@@ -45,13 +45,18 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """sha256 prefix of the code (comments and blank space removed) of the
+    kernels (t-sweep and checkerboard), their spinor I/O, the routing between
+    them and the site traversal order built at create."""
     import hashlib
+    import re
     h = hashlib.sha256()
-    # the kernels (t-sweep and checkerboard), their spinor I/O, the routing
-    # between them and the site traversal order built at create
     for f in ("sweep.hip", "hop.hip", "hopcore.h", "common.h", "siteio.h", "api.cpp"):
-        with open(os.path.join(HERE, "paper_2112_01852_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(HERE, "paper_2112_01852_amd", "csrc", f)) as fh:
+            code = fh.read()
+        code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 

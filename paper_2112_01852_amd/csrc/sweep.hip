@@ -5,23 +5,23 @@
 // neighbour spinors come from.
 //
 // The checkerboard kernel gathers all eight neighbour spinors of a 5D site
-// from memory, and at 32^4 x 16 those gathers, not the arithmetic, set its
-// time. Here a block owns one whole x-row (the Lx sites at fixed y, z, all 16
-// slices; lane = (x, s)) and walks it along t, one plane per step:
-//   * each lane keeps the spinors of its own column at t-1, t and t+1 in
-//     registers: they are the site's own term and its -t and +t neighbours,
-//     and each spinor of the field is loaded from memory once, by its owner;
-//   * the row's spinors at t are exchanged through LDS for the +-x
-//     neighbours (the row is periodic in x, so every x neighbour is there);
-//   * only the four y and z neighbours are gathered from memory, two
-//     directions in flight as in the checkerboard kernel;
+// through the vector memory path. Here a block owns one whole x-row (the Lx
+// sites at fixed y, z, all 16 slices; lane = (x, s)) and walks it along t,
+// one plane per step:
+//   * each lane loads its own column's spinor at t+1 once: it is the +t
+//     neighbour of this plane and goes into the row exchange for the next;
+//   * the row's spinors at t and t-1 sit in a double-buffered LDS exchange,
+//     which gives the +-x neighbours (the row is periodic in x), the -t
+//     neighbour and the site's own term (a lane reads its own slot back);
+//   * only the four y and z neighbours are gathered from memory, three of
+//     them issued at the top of the plane;
 //   * the 8 links of each site come from a doubled link field (U_mu(x) and
-//     U_mu(x - mu) contiguous per site), staged in LDS one step ahead and
-//     shared by the 16 slices.
+//     U_mu(x - mu) contiguous per site), staged in LDS one plane ahead and
+//     shared by the 16 slices; links and output bypass L2 (non-temporal).
 // That is five spinor loads per 5D site instead of nine. The rows an XCD
 // works on at one time form a compact (y, z) patch, so the y and z
-// neighbours its blocks gather were loaded moments earlier by the patch's
-// other blocks and are still in that XCD's L2.
+// neighbours its blocks gather were loaded one plane earlier by the patch's
+// other blocks and are mostly still in that XCD's L2.
 #include <cstdlib>
 #include <type_traits>
 
