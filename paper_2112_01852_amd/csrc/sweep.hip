@@ -245,7 +245,7 @@ sweep_kernel(SweepK k) {
   };
 
   const int t0 = tc * k.tl, tend = t0 + k.tl;
-  // own column at t and t+1, and the z neighbours at t
+  // own column at t and t+1, and the y and z neighbours at t
   int c0 = site(x, y, z, t0), c1 = site(x, y, z, t0 + 1);
   int nyp = site(x, yp, z, t0), nym = site(x, ym, z, t0);
   int nzp = site(x, y, zp, t0), nzm = site(x, y, zm, t0);
