@@ -18,7 +18,12 @@
 //   * the 8 links of each site come from a doubled link field (U_mu(x) and
 //     U_mu(x - mu) contiguous per site), staged in LDS one plane ahead and
 //     shared by the 16 slices; links and output bypass L2 (non-temporal).
-// That is five spinor loads per 5D site instead of nine. The rows an XCD
+// That is five spinor loads per 5D site instead of nine. For D (not D^dag,
+// 32-bit and FP16 storage) the row exchange holds chi = A psi / b rather than
+// psi, so the -t, +-x and +t hops take A once per loaded column instead of
+// once per neighbour; the site's own psi is then never read back: the
+// 5D term (alpha + beta C) psi, divided by the hop factor, seeds the
+// plane's accumulator when its column arrives, one plane ahead. The rows an XCD
 // works on at one time form a compact (y, z) patch, so the y and z
 // neighbours its blocks gather were loaded one plane earlier by the patch's
 // other blocks and are mostly still in that XCD's L2.
@@ -95,10 +100,11 @@ constexpr int LSTR = 20;    // reals per staged link (16-byte rows)
 // One hop direction D of a lane's 5D site, accumulated into acc: the
 // neighbour spinor src (raw psi), for D (not D^dag) first multiplied by
 // A / b = 1 + (c/b) C with the s +- 1 values from the neighbouring lanes of the
-// DPP row; projected to a half spinor, multiplied by the link at lks + D *
-// LSTR (U_mu(x) forward, U_mu(x - mu)^dag backward) and reconstructed.
+// DPP row unless PRE says src already holds A psi / b; projected to a half
+// spinor, multiplied by the link at lks + D * LSTR (U_mu(x) forward,
+// U_mu(x - mu)^dag backward) and reconstructed.
 // refill() runs once src has been read, so a buffer may be reloaded there.
-template <bool DAG, int D, bool FIRST, class Refill>
+template <bool DAG, int D, bool FIRST, class Refill, bool PRE = false>
 __device__ inline __attribute__((always_inline)) void dir_acc(
     const SShift<true>& sh, float cm, float cp, const float* lks, const float* src, float* acc,
     Refill refill) {
@@ -107,7 +113,7 @@ __device__ inline __attribute__((always_inline)) void dir_acc(
   // (1 - g) on forward hops and (1 + g) on backward ones; swapped for D^dag
   constexpr int SG = (FWD != DAG) ? -1 : +1;
   float v[24];
-  if constexpr (!DAG) {
+  if constexpr (!DAG && !PRE) {
     // chi / b = psi + (c/b) (P+ psi_{s-1} + P- psi_{s+1}), walls included
 #pragma unroll
     for (int i = 0; i < 12; ++i) v[i] = sh.fm(cm, src[i], src[i]);
@@ -155,6 +161,28 @@ __device__ inline __attribute__((always_inline)) void epilogue(
 #pragma unroll
     for (int i = 12; i < 24; ++i) acc[i] = sh.fm(bm, psi[i], acc[i]);
   }
+}
+
+// v = A psi / b = psi + (c/b) C psi for one lane (cm, cp: c/b times the wall
+// factors of S_d and S_u at this slice)
+__device__ inline __attribute__((always_inline)) void apply_a(
+    const SShift<true>& sh, float cm, float cp, const float* psi, float* v) {
+#pragma unroll
+  for (int i = 0; i < 12; ++i) v[i] = sh.fm(cm, psi[i], psi[i]);
+#pragma unroll
+  for (int i = 12; i < 24; ++i) v[i] = sh.fp(cp, psi[i], psi[i]);
+}
+
+// acc = (alpha psi + beta C psi) / (hop scale b): the 5D term of D in the
+// units of the hop sum, so that the plane's output is (hop scale b) acc
+__device__ inline __attribute__((always_inline)) void local_init(
+    const SShift<true>& sh, float ial, float ibm, float ibp, const float* psi, float* acc) {
+#pragma unroll
+  for (int i = 0; i < 24; ++i) acc[i] = ial * psi[i];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) acc[i] = sh.fm(ibm, psi[i], acc[i]);
+#pragma unroll
+  for (int i = 12; i < 24; ++i) acc[i] = sh.fp(ibp, psi[i], acc[i]);
 }
 
 template <class S, bool DAG, int W>
@@ -209,6 +237,11 @@ sweep_kernel(SweepK k) {
   const float wm = (s == 0) ? -mf : 1.0f;    // wall factor of S_d at this slice
   const float wp = (s == 15) ? -mf : 1.0f;   // wall factor of S_u at this slice
   const float cm = k.cob * wm, cp = k.cob * wp;
+  // D keeps chi = A psi / b in the row exchange (BF16 storage would spill)
+  constexpr bool CHI = !DAG && !std::is_same<S, bf16>::value;
+  const float ihs = 1.0f / k.hsb;
+  const float ial = k.alpha * ihs, ibm = k.beta * wm * ihs, ibp = k.beta * wp * ihs;
+  float acc[24];   // the plane's hop sum (with CHI: seeded one plane ahead)
 
   // link stage: this thread's 16-byte words of the row's doubled links
   uint4 lw[NCH];
@@ -268,9 +301,20 @@ sweep_kernel(SweepK k) {
     const int p0 = (x + pyz + t0) & 1;
     float w[24];
     ld(1 - p0, site(x, y, z, t0 - 1), w);
-    put(t0 - 1, w);   // the -t neighbour of the first plane
-    ld(p0, c0, w);
-    put(t0, w);
+    // the -t neighbour of the first plane, then the first plane itself
+    if constexpr (CHI) {
+      float v[24];
+      apply_a(sh, cm, cp, w, v);
+      put(t0 - 1, v);
+      ld(p0, c0, w);
+      apply_a(sh, cm, cp, w, v);
+      put(t0, v);
+      local_init(sh, ial, ibm, ibp, w, acc);
+    } else {
+      put(t0 - 1, w);
+      ld(p0, c0, w);
+      put(t0, w);
+    }
     if (s == 0) cbrow[t0 & 1][x] = c0;
     __syncthreads();
     stage_load(t0);
@@ -300,9 +344,16 @@ sweep_kernel(SweepK k) {
     if (more) stage_load(t + 1);
 
     const float* lks = Lk[t & 1] + x * 8 * LSTR;
-    float acc[24];
     auto dir = [&](auto Dc, auto Fc, const float* src, auto refill) __attribute__((always_inline)) {
       dir_acc<DAG, decltype(Dc)::value, decltype(Fc)::value>(sh, cm, cp, lks, src, acc, refill);
+    };
+    // a hop from the row exchange: with CHI it holds A psi / b, and acc is
+    // already seeded, so no direction starts the sum
+    auto xdir = [&](auto Dc, auto Fc, const float* src, auto refill) __attribute__((always_inline)) {
+      if constexpr (CHI)
+        dir_acc<DAG, decltype(Dc)::value, false, decltype(refill), true>(sh, cm, cp, lks, src, acc, refill);
+      else
+        dir_acc<DAG, decltype(Dc)::value, decltype(Fc)::value>(sh, cm, cp, lks, src, acc, refill);
     };
     auto none = [] {};
     {
@@ -310,31 +361,42 @@ sweep_kernel(SweepK k) {
       // the next plane (no other lane reads that buffer during this plane)
       float w[24];
       get(t - 1, x, w);
-      dir(IC<7>(), std::true_type(), w, none);
+      xdir(IC<7>(), std::true_type(), w, none);
     }
     {
       float w[24];
       get(t, xp, w);
-      dir(IC<0>(), std::false_type(), w, none);                              // +x
+      xdir(IC<0>(), std::false_type(), w, none);                             // +x
     }
     {
       float w[24];
       get(t, xm, w);
-      dir(IC<4>(), std::false_type(), w, none);                              // -x
+      xdir(IC<4>(), std::false_type(), w, none);                             // -x
     }
     dir(IC<1>(), std::false_type(), va, [&] { ld(q, nzm, va); });           // +y; then -z
     dir(IC<5>(), std::false_type(), vb, none);                               // -y
     dir(IC<2>(), std::false_type(), vc, none);                               // +z
     dir(IC<6>(), std::false_type(), va, none);                               // -z
-    dir(IC<3>(), std::false_type(), R, [&] { put(t + 1, R); });             // +t
-
-    {
-      // psi of the own site, read back from the lane's exchange slot
-      float z0[24];
-      get(t, x, z0);
-      epilogue<DAG>(sh, cm, cp, k.hsb, k.alpha, k.beta * wm, k.beta * wp, z0, acc);
+    if constexpr (CHI) {
+      // +t from the column just loaded, which as A psi / b becomes the next
+      // plane's exchange; its psi seeds the next plane's sum
+      float v[24];
+      apply_a(sh, cm, cp, R, v);
+      xdir(IC<3>(), std::false_type(), v, [&] { put(t + 1, v); });
+#pragma unroll
+      for (int i = 0; i < 24; ++i) acc[i] *= k.hsb;
+      store_nt(O + p * k.half, c0, acc);
+      local_init(sh, ial, ibm, ibp, R, acc);
+    } else {
+      dir(IC<3>(), std::false_type(), R, [&] { put(t + 1, R); });           // +t
+      {
+        // psi of the own site, read back from the lane's exchange slot
+        float z0[24];
+        get(t, x, z0);
+        epilogue<DAG>(sh, cm, cp, k.hsb, k.alpha, k.beta * wm, k.beta * wp, z0, acc);
+      }
+      store_nt(O + p * k.half, c0, acc);
     }
-    store_nt(O + p * k.half, c0, acc);
     c0 = c1; c1 = c2;
     nyp = nyp1; nym = nym1; nzp = nzp1; nzm = nzm1;
   }
@@ -385,7 +447,7 @@ bool sweep_eligible(const qdwf_ctx* ctx, int prec, int layout, const HopArgs& a)
   if (!sweep_geometry(ctx->g) || layout != QDWF_RIRI) return false;
   if (prec != QDWF_F32 && prec != QDWF_F16 && prec != QDWF_BF16) return false;
   if (!ctx->d_dlinks[prec]) return false;
-  if (a.npar != 2 || a.par0 != 0 || !a.epi || a.minv || a.links) return false;
+  if (a.npar != 2 || a.par0 != 0 || !a.epi || a.minv || a.links || a.hop_scale == 0.0) return false;
   // one full field: in[p] is the other parity's half, z[p] this parity's
   const long half = ctx->g.n5h * 24;
   const size_t hb = (size_t)half * prec_bytes(prec);
