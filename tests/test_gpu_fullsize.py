@@ -1,8 +1,8 @@
 """The benchmark workload itself: Mobius D and D^dag on the full 32^4 x 16
 lattice, with the benchmark's inputs (Haar links seed 2000, Gaussian spinor
 seed 2001, drawn in single precision as the benchmark draws them) and the
-launch configuration it times (default shape, RIRI: the t-sweep for FP32),
-with the checkerboard kernel and the FP16 t-sweep forced as extra cases,
+launch configuration it times (default shape, RIRI: the t-sweep for FP32
+and FP16 storage), with the checkerboard kernel forced as extra cases,
 read back on sampled 5D sites and compared with the FP64 oracle evaluated
 site by site on the same inputs widened to FP64.
 
@@ -58,11 +58,11 @@ def full():
 
 
 @pytest.mark.parametrize("prec,dagger,form", [(1, 0, ""), (1, 1, ""), (1, 0, "0"), (1, 1, "0"),
-                                              (0, 0, ""), (2, 0, ""), (2, 0, "1")])
+                                              (0, 0, ""), (2, 0, ""), (2, 0, "0")])
 def test_full_lattice_sampled_sites(full, prec, dagger, form, monkeypatch):
-    """form: "" the library's default (the t-sweep for FP32 at this size, the
-    checkerboard kernel otherwise), "0" / "1" the checkerboard kernel / the
-    t-sweep forced."""
+    """form: "" the library's default (the t-sweep for FP32 and FP16 storage
+    at this size, the checkerboard kernel for FP64), "0" / "1" the
+    checkerboard kernel / the t-sweep forced."""
     q, torch, a, U, psi, psi_d, D, idx = full
     if form:
         monkeypatch.setenv("QDWF_SWEEP", form)

@@ -61,7 +61,8 @@ def case(q, request):
 
 @pytest.fixture(autouse=True)
 def force_sweep(monkeypatch):
-    """The sweep is the default only for 16- and 32-wide rows: force it."""
+    """The sweep is the default only for FP32 in 16- and 32-wide rows and FP16
+    in 32-wide rows: force it."""
     monkeypatch.setenv("QDWF_SWEEP", "1")
 
 
