@@ -193,7 +193,7 @@ sweep_kernel(SweepK k) {
   constexpr int E = 16 / (int)sizeof(S);
   constexpr int CPS = 144 / E;
   constexpr int NCH = (W * CPS + NT - 1) / NT;
-  __shared__ __align__(16) float X[2][W * SITE];        // the row's spinors at t
+  __shared__ __align__(16) float X[2][W * SITE];        // the row at t (psi, or A psi / b)
   __shared__ __align__(16) float Lk[2][W * 8 * LSTR];   // the row's links at t
   __shared__ int cbrow[2][W];                            // the row's sites at t
 
@@ -323,8 +323,8 @@ sweep_kernel(SweepK k) {
   for (int t = t0; t < tend; ++t) {
     const int p = (x + pyz + t) & 1, q = 1 - p;
     const bool more = t + 1 < tend;
-    // publish this plane's links (the row's spinors at t are already in
-    // X[t & 1]) and the sites of the next plane for its link stage
+    // publish this plane's links (the row at t is already in X[t & 1])
+    // and the sites of the next plane for its link stage
     stage_store(t);
     if (s == 0) cbrow[(t + 1) & 1][x] = c1;
     __syncthreads();
