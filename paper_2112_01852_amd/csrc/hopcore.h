@@ -63,6 +63,13 @@ template <int R> __device__ inline int dpp_ror(int v) {
 #define QDWF_FMAC_ROR(R)                                                              \
   asm("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_ror:" #R " row_mask:0xf bank_mask:0xf" \
       : "+v"(a) : "v"(x), "v"(c))
+// six of them, a[j] += c x[j](lane - R), after one s_nop
+#define QDWF_DPP_ROR(R, D, X) "\n\tv_fmac_f32_dpp %" #D ", %" #X ", %12 row_ror:" #R " row_mask:0xf bank_mask:0xf"
+#define QDWF_FMAC_ROR6(R)                                                             \
+  asm("s_nop 1" QDWF_DPP_ROR(R, 0, 6) QDWF_DPP_ROR(R, 1, 7) QDWF_DPP_ROR(R, 2, 8)      \
+      QDWF_DPP_ROR(R, 3, 9) QDWF_DPP_ROR(R, 4, 10) QDWF_DPP_ROR(R, 5, 11)               \
+      : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5])          \
+      : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(x[3]), "v"(x[4]), "v"(x[5]), "v"(c))
 template <> struct SShift<true> {
   int src_m, src_p;
   // a + c x(lane - R), R = 1..15, within the 16-lane row
@@ -85,7 +92,27 @@ template <> struct SShift<true> {
   }
   template <class T> __device__ inline T fm(T c, T x, T a) const { return fr<1>(c, x, a); }
   template <class T> __device__ inline T fp(T c, T x, T a) const { return fr<15>(c, x, a); }
+  // v[0..11] += cu x[0..11](lane - RU) and v[12..23] += cl x[12..23](lane -
+  // RL) for one 24-real spinor (RU, RL = 1: from s-1, 15: from s+1): four
+  // groups of six DPP FMAs, each behind a single pair of wait states. Within
+  // a group the six sources are distinct registers that none of the six FMAs
+  // writes (each is a different value live at the group's start, and an
+  // output can share a register only with its own input), so no FMA reads a
+  // register the group has just written.
+  template <int RU, int RL>
+  __device__ inline void shift24(float cu, float cl, const float* x, float* v) const {
+    fr6<RU>(cu, x, v);
+    fr6<RU>(cu, x + 6, v + 6);
+    fr6<RL>(cl, x + 12, v + 12);
+    fr6<RL>(cl, x + 18, v + 18);
+  }
+  template <int R> __device__ inline void fr6(float c, const float* x, float* a) const {
+    static_assert(R == 1 || R == 15, "rotation not instantiated");
+    if constexpr (R == 1) QDWF_FMAC_ROR6(1);
+    else QDWF_FMAC_ROR6(15);
+  }
 };
 #undef QDWF_FMAC_ROR
+#undef QDWF_FMAC_ROR6
 
 }  // namespace qdwf

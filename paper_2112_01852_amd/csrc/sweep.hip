@@ -116,9 +116,8 @@ __device__ inline __attribute__((always_inline)) void dir_acc(
   if constexpr (!DAG && !PRE) {
     // chi / b = psi + (c/b) (P+ psi_{s-1} + P- psi_{s+1}), walls included
 #pragma unroll
-    for (int i = 0; i < 12; ++i) v[i] = sh.fm(cm, src[i], src[i]);
-#pragma unroll
-    for (int i = 12; i < 24; ++i) v[i] = sh.fp(cp, src[i], src[i]);
+    for (int i = 0; i < 24; ++i) v[i] = src[i];
+    sh.shift24<1, 15>(cm, cp, src, v);
   } else {
 #pragma unroll
     for (int i = 0; i < 24; ++i) v[i] = src[i];
@@ -142,25 +141,17 @@ __device__ inline __attribute__((always_inline)) void epilogue(
     // A^dag h / b = h + (c/b) C^dag h: upper spins from s+1, lower from s-1
     float tmp[24];
 #pragma unroll
-    for (int i = 0; i < 12; ++i) tmp[i] = sh.fp(cp, acc[i], acc[i]);
-#pragma unroll
-    for (int i = 12; i < 24; ++i) tmp[i] = sh.fm(cm, acc[i], acc[i]);
+    for (int i = 0; i < 24; ++i) tmp[i] = acc[i];
+    sh.shift24<15, 1>(cp, cm, acc, tmp);
 #pragma unroll
     for (int i = 0; i < 24; ++i) acc[i] = tmp[i];
   }
 #pragma unroll
   for (int i = 0; i < 24; ++i) acc[i] = fmac(al, psi[i], hs * acc[i]);
-  if constexpr (!DAG) {
-#pragma unroll
-    for (int i = 0; i < 12; ++i) acc[i] = sh.fm(bm, psi[i], acc[i]);
-#pragma unroll
-    for (int i = 12; i < 24; ++i) acc[i] = sh.fp(bp, psi[i], acc[i]);
-  } else {
-#pragma unroll
-    for (int i = 0; i < 12; ++i) acc[i] = sh.fp(bp, psi[i], acc[i]);
-#pragma unroll
-    for (int i = 12; i < 24; ++i) acc[i] = sh.fm(bm, psi[i], acc[i]);
-  }
+  if constexpr (!DAG)
+    sh.shift24<1, 15>(bm, bp, psi, acc);
+  else
+    sh.shift24<15, 1>(bp, bm, psi, acc);
 }
 
 // v = A psi / b = psi + (c/b) C psi for one lane (cm, cp: c/b times the wall
@@ -168,9 +159,8 @@ __device__ inline __attribute__((always_inline)) void epilogue(
 __device__ inline __attribute__((always_inline)) void apply_a(
     const SShift<true>& sh, float cm, float cp, const float* psi, float* v) {
 #pragma unroll
-  for (int i = 0; i < 12; ++i) v[i] = sh.fm(cm, psi[i], psi[i]);
-#pragma unroll
-  for (int i = 12; i < 24; ++i) v[i] = sh.fp(cp, psi[i], psi[i]);
+  for (int i = 0; i < 24; ++i) v[i] = psi[i];
+  sh.shift24<1, 15>(cm, cp, psi, v);
 }
 
 // acc = (alpha psi + beta C psi) / (hop scale b): the 5D term of D in the
@@ -179,10 +169,7 @@ __device__ inline __attribute__((always_inline)) void local_init(
     const SShift<true>& sh, float ial, float ibm, float ibp, const float* psi, float* acc) {
 #pragma unroll
   for (int i = 0; i < 24; ++i) acc[i] = ial * psi[i];
-#pragma unroll
-  for (int i = 0; i < 12; ++i) acc[i] = sh.fm(ibm, psi[i], acc[i]);
-#pragma unroll
-  for (int i = 12; i < 24; ++i) acc[i] = sh.fp(ibp, psi[i], acc[i]);
+  sh.shift24<1, 15>(ibm, ibp, psi, acc);
 }
 
 template <class S, bool DAG, int W>

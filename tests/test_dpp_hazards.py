@@ -1,0 +1,71 @@
+"""Static check of the t-sweep's grouped DPP FMAs in the gfx950 assembly.
+
+The sweep applies the s +- 1 shifts of the fifth dimension with
+v_fmac_f32_dpp (row rotates), written as inline assembly in groups of six
+behind one `s_nop 1`: the two wait states a DPP read needs after a VALU write
+of its source cover the whole group only if no FMA in a group reads (through
+DPP or as its multiplier) a register that an earlier FMA of the same group
+wrote. The helper guarantees that by construction (distinct live values get
+distinct registers); this test compiles sweep.hip for gfx950 exactly as the
+build does and checks every group in the generated code, so that a compiler
+that allocated registers otherwise would be caught on the CPU.
+"""
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2112_01852_amd import build as B
+
+
+def _hipcc():
+    try:
+        return B.hipcc()
+    except RuntimeError:
+        return None
+
+
+PAT = re.compile(r"v_fmac_f32_dpp\s+(v\d+),\s*(v\d+),\s*(v\d+)")
+
+
+def _groups(lines):
+    """Number of DPP FMA runs; AssertionError on a run that does not follow
+    an s_nop 1, is longer than six, or reads a register written earlier in
+    the run."""
+    groups, i = 0, 0
+    while i < len(lines):
+        if lines[i].startswith("v_fmac_f32_dpp"):
+            assert i > 0 and lines[i - 1] == "s_nop 1", (i, lines[i - 1], lines[i])
+            written = set()
+            while i < len(lines) and lines[i].startswith("v_fmac_f32_dpp"):
+                dst, src, mul = PAT.match(lines[i]).groups()
+                assert src not in written and mul not in written, (i, lines[i], sorted(written))
+                written.add(dst)
+                i += 1
+            assert len(written) <= 6
+            groups += 1
+        else:
+            i += 1
+    return groups
+
+
+def test_checker_catches_a_hazard():
+    ok = ["s_nop 1", "v_fmac_f32_dpp v10, v20, v1 row_ror:1", "v_fmac_f32_dpp v11, v21, v1 row_ror:1"]
+    assert _groups(ok) == 1
+    with pytest.raises(AssertionError):
+        _groups(["s_nop 1", "v_fmac_f32_dpp v10, v20, v1 row_ror:1", "v_fmac_f32_dpp v11, v10, v1 row_ror:1"])
+    with pytest.raises(AssertionError):
+        _groups(["v_add_f32_e32 v20, v2, v3", "v_fmac_f32_dpp v10, v20, v1 row_ror:1"])
+
+
+@pytest.mark.skipif(_hipcc() is None, reason="hipcc not available")
+def test_grouped_dpp_fmas_read_no_register_written_in_their_group(tmp_path):
+    out = tmp_path / "sweep.s"
+    cmd = [_hipcc(), "-x", "hip", f"--offload-arch={B.ARCH}", "-O3", "-std=c++17",
+           "-I", B.INCLUDE, "-I", B.CSRC, *B.DEVICE_FLAGS, "--cuda-device-only", "-S",
+           os.path.join(B.CSRC, "sweep.hip"), "-o", str(out)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [l.strip() for l in out.read_text().splitlines()]
+    assert _groups(lines) > 0
