@@ -149,10 +149,10 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_ker
       SiteIO<S, LAYOUT>::load(in, nbs[(D + 2) * k.nsb], s, Ls, k.plane, buf);
     if constexpr (!DAG) {
       // chi / b = psi + (c/b) (P+ psi_{s-1} + P- psi_{s+1}), walls included
+      T w[24];
 #pragma unroll
-      for (int i = 0; i < 12; ++i) v[i] = sh.fm(cm, v[i], v[i]);
-#pragma unroll
-      for (int i = 12; i < 24; ++i) v[i] = sh.fp(cp, v[i], v[i]);
+      for (int i = 0; i < 24; ++i) w[i] = v[i];
+      shift_s<1, 15>(sh, cm, cp, w, v);
     }
     T h[12], uh[12], U[18];
     load_link(lks + D * LSTR, U);
@@ -168,9 +168,8 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_ker
     // upper spins come from s+1, lower spins from s-1
     T tmp[24];
 #pragma unroll
-    for (int i = 0; i < 12; ++i) tmp[i] = sh.fp(cp, acc[i], acc[i]);
-#pragma unroll
-    for (int i = 12; i < 24; ++i) tmp[i] = sh.fm(cm, acc[i], acc[i]);
+    for (int i = 0; i < 24; ++i) tmp[i] = acc[i];
+    shift_s<15, 1>(sh, cp, cm, acc, tmp);
 #pragma unroll
     for (int i = 0; i < 24; ++i) acc[i] = tmp[i];
   }
@@ -188,14 +187,11 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_ker
         const T rp = (T)k.rpow[J];
         const T cdn = (s - Dd < 0) ? rp * (-mf) : rp;    // source slice s - d
         const T cup = (s + Dd >= 16) ? rp * (-mf) : rp;  // source slice s + d
+        T src[24];
 #pragma unroll
-        for (int i = 0; i < 12; ++i)
-          acc[i] = DAG ? sh.template fr<16 - Dd>(cup, acc[i], acc[i])
-                       : sh.template fr<Dd>(cdn, acc[i], acc[i]);
-#pragma unroll
-        for (int i = 12; i < 24; ++i)
-          acc[i] = DAG ? sh.template fr<Dd>(cdn, acc[i], acc[i])
-                       : sh.template fr<16 - Dd>(cup, acc[i], acc[i]);
+        for (int i = 0; i < 24; ++i) src[i] = acc[i];
+        if constexpr (DAG) shift_s<16 - Dd, Dd>(sh, cup, cdn, src, acc);
+        else shift_s<Dd, 16 - Dd>(sh, cdn, cup, src, acc);
       };
       scan(IC<0>()); scan(IC<1>()); scan(IC<2>()); scan(IC<3>());
     }
@@ -209,17 +205,8 @@ __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_ker
     const T bm = be * wm, bp = be * wp;
 #pragma unroll
     for (int i = 0; i < 24; ++i) acc[i] = fmac(al, z[i], hs * acc[i]);
-    if constexpr (!DAG) {  // + beta C z
-#pragma unroll
-      for (int i = 0; i < 12; ++i) acc[i] = sh.fm(bm, z[i], acc[i]);
-#pragma unroll
-      for (int i = 12; i < 24; ++i) acc[i] = sh.fp(bp, z[i], acc[i]);
-    } else {               // + beta C^dag z
-#pragma unroll
-      for (int i = 0; i < 12; ++i) acc[i] = sh.fp(bp, z[i], acc[i]);
-#pragma unroll
-      for (int i = 12; i < 24; ++i) acc[i] = sh.fm(bm, z[i], acc[i]);
-    }
+    if constexpr (!DAG) shift_s<1, 15>(sh, bm, bp, z, acc);   // + beta C z
+    else shift_s<15, 1>(sh, bp, bm, z, acc);                  // + beta C^dag z
   } else {
 #pragma unroll
     for (int i = 0; i < 24; ++i) acc[i] *= hs;

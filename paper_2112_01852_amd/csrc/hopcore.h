@@ -107,11 +107,39 @@ template <> struct SShift<true> {
     fr6<RL>(cl, x + 18, v + 18);
   }
   template <int R> __device__ inline void fr6(float c, const float* x, float* a) const {
-    static_assert(R == 1 || R == 15, "rotation not instantiated");
+    static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 12 || R == 14 || R == 15,
+                  "rotation not instantiated");
     if constexpr (R == 1) QDWF_FMAC_ROR6(1);
+    else if constexpr (R == 2) QDWF_FMAC_ROR6(2);
+    else if constexpr (R == 4) QDWF_FMAC_ROR6(4);
+    else if constexpr (R == 8) QDWF_FMAC_ROR6(8);
+    else if constexpr (R == 12) QDWF_FMAC_ROR6(12);
+    else if constexpr (R == 14) QDWF_FMAC_ROR6(14);
     else QDWF_FMAC_ROR6(15);
   }
 };
+
+// v[0..11] += cu x[0..11](s - RU) and v[12..23] += cu x[12..23](s - RL), s
+// cyclic over the Ls slices (R = 1: from s - 1, R = Ls - 1: from s + 1). FP32
+// on the DPP path goes six FMAs to a wait-state pair (SShift<true>::shift24);
+// FP64 and the permute path (which knows only s -+ 1) go element by element.
+template <int RU, int RL, bool DPP16, class T>
+__device__ inline void shift_s(const SShift<DPP16>& sh, T cu, T cl, const T* x, T* v) {
+  if constexpr (DPP16 && sizeof(T) == 4) {
+    sh.template shift24<RU, RL>(cu, cl, x, v);
+  } else if constexpr (DPP16) {
+#pragma unroll
+    for (int i = 0; i < 12; ++i) v[i] = sh.template fr<RU>(cu, x[i], v[i]);
+#pragma unroll
+    for (int i = 12; i < 24; ++i) v[i] = sh.template fr<RL>(cl, x[i], v[i]);
+  } else {
+    static_assert((RU == 1 && RL == 15) || (RU == 15 && RL == 1), "permute path shifts by one slice");
+#pragma unroll
+    for (int i = 0; i < 12; ++i) v[i] = RU == 1 ? sh.fm(cu, x[i], v[i]) : sh.fp(cu, x[i], v[i]);
+#pragma unroll
+    for (int i = 12; i < 24; ++i) v[i] = RL == 1 ? sh.fm(cl, x[i], v[i]) : sh.fp(cl, x[i], v[i]);
+  }
+}
 #undef QDWF_FMAC_ROR
 #undef QDWF_FMAC_ROR6
 

@@ -1,13 +1,15 @@
-"""Static check of the t-sweep's grouped DPP FMAs in the gfx950 assembly.
+"""Static check of the grouped DPP FMAs of the hop kernels in the gfx950
+assembly.
 
-The sweep applies the s +- 1 shifts of the fifth dimension with
-v_fmac_f32_dpp (row rotates), written as inline assembly in groups of six
-behind one `s_nop 1`: the two wait states a DPP read needs after a VALU write
+The t-sweep and the checkerboard kernel apply the shifts of the fifth
+dimension (s +- 1, and s +- 2^j in the M_ee^-1 scan) with v_fmac_f32_dpp
+(row rotates), written as inline assembly in groups of six behind one
+`s_nop 1`: the two wait states a DPP read needs after a VALU write
 of its source cover the whole group only if no FMA in a group reads (through
 DPP or as its multiplier) a register that an earlier FMA of the same group
 wrote. The helper guarantees that by construction (distinct live values get
-distinct registers); this test compiles sweep.hip for gfx950 exactly as the
-build does and checks every group in the generated code, so that a compiler
+distinct registers); this test compiles sweep.hip and hop.hip for gfx950
+exactly as the build does and checks every group in the generated code, so that a compiler
 that allocated registers otherwise would be caught on the CPU.
 """
 import os
@@ -60,11 +62,12 @@ def test_checker_catches_a_hazard():
 
 
 @pytest.mark.skipif(_hipcc() is None, reason="hipcc not available")
-def test_grouped_dpp_fmas_read_no_register_written_in_their_group(tmp_path):
-    out = tmp_path / "sweep.s"
+@pytest.mark.parametrize("src", ["sweep.hip", "hop.hip"])
+def test_grouped_dpp_fmas_read_no_register_written_in_their_group(tmp_path, src):
+    out = tmp_path / (src + ".s")
     cmd = [_hipcc(), "-x", "hip", f"--offload-arch={B.ARCH}", "-O3", "-std=c++17",
            "-I", B.INCLUDE, "-I", B.CSRC, *B.DEVICE_FLAGS, "--cuda-device-only", "-S",
-           os.path.join(B.CSRC, "sweep.hip"), "-o", str(out)]
+           os.path.join(B.CSRC, src), "-o", str(out)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [l.strip() for l in out.read_text().splitlines()]
