@@ -70,6 +70,13 @@ template <int R> __device__ inline int dpp_ror(int v) {
       QDWF_DPP_ROR(R, 3, 9) QDWF_DPP_ROR(R, 4, 10) QDWF_DPP_ROR(R, 5, 11)               \
       : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5])          \
       : "v"(x[0]), "v"(x[1]), "v"(x[2]), "v"(x[3]), "v"(x[4]), "v"(x[5]), "v"(c))
+// in place: a[j] += c a[j](lane - R), each FMA's DPP source its own register
+#define QDWF_DPP_ROR_IP(R, D) "\n\tv_fmac_f32_dpp %" #D ", %" #D ", %6 row_ror:" #R " row_mask:0xf bank_mask:0xf"
+#define QDWF_FMAC_ROR6_IP(R)                                                          \
+  asm("s_nop 1" QDWF_DPP_ROR_IP(R, 0) QDWF_DPP_ROR_IP(R, 1) QDWF_DPP_ROR_IP(R, 2)      \
+      QDWF_DPP_ROR_IP(R, 3) QDWF_DPP_ROR_IP(R, 4) QDWF_DPP_ROR_IP(R, 5)                 \
+      : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5])          \
+      : "v"(c))
 template <> struct SShift<true> {
   int src_m, src_p;
   // a + c x(lane - R), R = 1..15, within the 16-lane row
@@ -105,6 +112,24 @@ template <> struct SShift<true> {
     fr6<RU>(cu, x + 6, v + 6);
     fr6<RL>(cl, x + 12, v + 12);
     fr6<RL>(cl, x + 18, v + 18);
+  }
+  // the same in place, v += c v(shifted): no source copies
+  template <int RU, int RL> __device__ inline void shift24i(float cu, float cl, float* v) const {
+    fr6i<RU>(cu, v);
+    fr6i<RU>(cu, v + 6);
+    fr6i<RL>(cl, v + 12);
+    fr6i<RL>(cl, v + 18);
+  }
+  template <int R> __device__ inline void fr6i(float c, float* a) const {
+    static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 12 || R == 14 || R == 15,
+                  "rotation not instantiated");
+    if constexpr (R == 1) QDWF_FMAC_ROR6_IP(1);
+    else if constexpr (R == 2) QDWF_FMAC_ROR6_IP(2);
+    else if constexpr (R == 4) QDWF_FMAC_ROR6_IP(4);
+    else if constexpr (R == 8) QDWF_FMAC_ROR6_IP(8);
+    else if constexpr (R == 12) QDWF_FMAC_ROR6_IP(12);
+    else if constexpr (R == 14) QDWF_FMAC_ROR6_IP(14);
+    else QDWF_FMAC_ROR6_IP(15);
   }
   template <int R> __device__ inline void fr6(float c, const float* x, float* a) const {
     static_assert(R == 1 || R == 2 || R == 4 || R == 8 || R == 12 || R == 14 || R == 15,
@@ -142,5 +167,6 @@ __device__ inline void shift_s(const SShift<DPP16>& sh, T cu, T cl, const T* x, 
 }
 #undef QDWF_FMAC_ROR
 #undef QDWF_FMAC_ROR6
+#undef QDWF_FMAC_ROR6_IP
 
 }  // namespace qdwf

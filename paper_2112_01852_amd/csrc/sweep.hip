@@ -117,7 +117,7 @@ __device__ inline __attribute__((always_inline)) void dir_acc(
     // chi / b = psi + (c/b) (P+ psi_{s-1} + P- psi_{s+1}), walls included
 #pragma unroll
     for (int i = 0; i < 24; ++i) v[i] = src[i];
-    sh.shift24<1, 15>(cm, cp, src, v);
+    sh.shift24i<1, 15>(cm, cp, v);
   } else {
 #pragma unroll
     for (int i = 0; i < 24; ++i) v[i] = src[i];
@@ -139,12 +139,7 @@ __device__ inline __attribute__((always_inline)) void epilogue(
     const float* psi, float* acc) {
   if constexpr (DAG) {
     // A^dag h / b = h + (c/b) C^dag h: upper spins from s+1, lower from s-1
-    float tmp[24];
-#pragma unroll
-    for (int i = 0; i < 24; ++i) tmp[i] = acc[i];
-    sh.shift24<15, 1>(cp, cm, acc, tmp);
-#pragma unroll
-    for (int i = 0; i < 24; ++i) acc[i] = tmp[i];
+    sh.shift24i<15, 1>(cp, cm, acc);
   }
 #pragma unroll
   for (int i = 0; i < 24; ++i) acc[i] = fmac(al, psi[i], hs * acc[i]);
@@ -160,7 +155,7 @@ __device__ inline __attribute__((always_inline)) void apply_a(
     const SShift<true>& sh, float cm, float cp, const float* psi, float* v) {
 #pragma unroll
   for (int i = 0; i < 24; ++i) v[i] = psi[i];
-  sh.shift24<1, 15>(cm, cp, psi, v);
+  sh.shift24i<1, 15>(cm, cp, v);
 }
 
 // acc = (alpha psi + beta C psi) / (hop scale b): the 5D term of D in the
