@@ -7,12 +7,12 @@
  * Argument checks happen before any device work, so a call that returns
  * QDWF_EINVAL has launched nothing. No exception or abort crosses the ABI.
  *
- * What is computed (the paper, arXiv 2112.01852, Sections 4.1-4.3, names the
- * Domain Wall kernel -- the 4D Wilson hopping term with SU(3) link multiplies
- * applied on every slice of the fifth dimension -- as the performance-relevant
- * part of the domain-wall operator, and counts 1320 real flops per 5D site for
- * it in Table 3; the operator itself is not written out in the paper, so the
- * standard conventions below are the definitions used):
+ * What is computed (the paper, arXiv 2112.01852, Sections 4.1-4.3, measures
+ * the Domain Wall kernel -- the 4D Wilson hopping term with SU(3) link
+ * multiplies applied on every slice of the fifth dimension -- and counts 1320
+ * real flops per 5D site for it in Table 3; the operator itself is not written
+ * out in the paper, so the standard conventions below are the definitions
+ * used):
  *
  *   lattice     L = (Lx, Ly, Lz, Lt), all even; lex = ((t*Lz+z)*Ly+y)*Lx+x;
  *               parity = (x+y+z+t) mod 2.

@@ -13,8 +13,8 @@
 // What the paper fixes, and what the code below takes as its definition:
 // * The paper (Sections 4.1-4.3) names the Domain Wall kernel -- the 4D Wilson
 //   hopping term with SU(3) link multiplies applied on every slice of the fifth
-//   dimension -- as the performance-relevant part of the domain-wall operator,
-//   and counts 1320 real flops per 5D site update for it (Table 3).
+//   dimension -- as the kernel whose speed it measures (Section 4.1), and
+//   counts 1320 real flops per 5D site update for it (Table 3).
 // * The paper writes neither the operator nor a solver as formulas, so the
 //   standard lattice-QCD conventions below are the reading taken (each is
 //   pinned by a closed form, an invariant or brute force in the CPU tests):

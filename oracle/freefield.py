@@ -37,10 +37,12 @@ def c_momentum(Ls: int, mf: float) -> np.ndarray:
     return np.kron(Su, Pm) + np.kron(Sd, Pp)
 
 
-def dwf_momentum(a, p) -> np.ndarray:
-    """D(p) on (s, spin), shape (4 Ls, 4 Ls)."""
+def dwf_momentum(a, p, C=None) -> np.ndarray:
+    """D(p) on (s, spin), shape (4 Ls, 4 Ls). C (which does not depend on p)
+    may be passed in when many momenta are evaluated."""
     W = wilson_momentum(p, a.M5)
-    C = c_momentum(a.Ls, a.mf)
+    if C is None:
+        C = c_momentum(a.Ls, a.mf)
     I = np.eye(4 * a.Ls)
     return np.kron(np.eye(a.Ls), W) @ (a.b * I + a.c * C) + (I - C)
 
@@ -58,8 +60,19 @@ def fft_solve(a, b: np.ndarray) -> np.ndarray:
     """Exact solution of D x = b for unit links, by Fourier transform.
 
     Antiperiodic directions are made periodic by the twist exp(-i pi x_mu / L_mu);
-    each momentum then needs one (4 Ls) x (4 Ls) solve per colour.
+    each momentum then needs one (4 Ls) x (4 Ls) solve per colour. b may carry
+    a leading axis of several right-hand sides, which share each momentum's
+    D(p).
     """
+    if b.ndim == 8:
+        n = b.shape[0]
+        cols = np.moveaxis(b, 0, -1).reshape(b.shape[1:-1] + (3 * n,))
+        x = _fft_solve_cols(a, cols)
+        return np.moveaxis(x.reshape(b.shape[1:-1] + (3, n)), -1, 0)
+    return _fft_solve_cols(a, b)
+
+
+def _fft_solve_cols(a, b: np.ndarray) -> np.ndarray:
     Lx, Ly, Lz, Lt = a.L
     L = a.L
     grids = np.meshgrid(np.arange(Lt), np.arange(Lz), np.arange(Ly), np.arange(Lx), indexing="ij")
@@ -71,13 +84,15 @@ def fft_solve(a, b: np.ndarray) -> np.ndarray:
     bt = b * tw[None, :, :, :, :, None, None]
     B = np.fft.fftn(bt, axes=(1, 2, 3, 4))
     X = np.empty_like(B)
+    C = c_momentum(a.Ls, a.mf)
+    nc = B.shape[-1]
     for kt in range(Lt):
         for kz in range(Lz):
             for ky in range(Ly):
                 for kx in range(Lx):
                     p = momenta(L, a.bc, (kx, ky, kz, kt))
-                    D = dwf_momentum(a, p)
-                    rhs = B[:, kt, kz, ky, kx, :, :].reshape(4 * a.Ls, 3)
-                    X[:, kt, kz, ky, kx, :, :] = np.linalg.solve(D, rhs).reshape(a.Ls, 4, 3)
+                    D = dwf_momentum(a, p, C)
+                    rhs = B[:, kt, kz, ky, kx, :, :].reshape(4 * a.Ls, nc)
+                    X[:, kt, kz, ky, kx, :, :] = np.linalg.solve(D, rhs).reshape(a.Ls, 4, nc)
     xt = np.fft.ifftn(X, axes=(1, 2, 3, 4))
     return xt / tw[None, :, :, :, :, None, None]

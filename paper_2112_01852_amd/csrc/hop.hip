@@ -1,6 +1,6 @@
 // The Domain Wall kernel: the 4D Wilson hop D_h applied on every slice of the
-// fifth dimension (the paper's "performance-relevant part of the Domain Wall
-// operator", Section 4.1; 1320 flops per 5D site in Table 3), fused with the
+// fifth dimension (the kernel Section 4.1 measures; 1320 flops per 5D site in
+// Table 3), fused with the
 // Mobius 5D factors and the 4D-local epilogue so that one pass over memory
 // gives D, D^dag, M_pq, (M_qp)^dag, or the last stage of M_pc / M_pc^dag.
 //

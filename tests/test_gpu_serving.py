@@ -44,6 +44,20 @@ def test_served_equals_alone_and_respects_budget(env):
         rc, st, dt, alone = serve.solo_solve(p, params)
         assert rc == q.QDWF_OK
         assert torch.equal(p.x, alone), f"request {i} differs between served and alone"
+        assert _oracle_residual(p) <= 1.5e-10, i
+
+
+def _oracle_residual(p):
+    """|b_o - M_pc^dag M_pc x_o| / |b_o| of a served result, with the oracle's
+    FP64 operator on the request's own links, mass and source."""
+    from oracle import cpu
+    sp = p.spec
+    a = cpu.Action(L=sp.L, Ls=sp.Ls, mf=sp.mf, M5=1.8, b=1.5, c=0.5)
+    U = p.U.cpu().numpy()
+    b = cpu.restrict(p.b.cpu().numpy(), sp.L, 1)
+    x = cpu.restrict(p.x.cpu().numpy(), sp.L, 1)
+    r = b - cpu.mpc(a, U, cpu.mpc(a, U, x), dagger=True)
+    return float(np.linalg.norm(r) / np.linalg.norm(b))
 
 
 def test_mixed_inner_precisions_converge(env):
@@ -56,6 +70,7 @@ def test_mixed_inner_precisions_converge(env):
         for i in range(3):
             assert res["status"][i] == q.QDWF_OK
             assert res["stats"][i]["true_residual"] <= 1e-10
+            assert _oracle_residual(prepared[i]) <= 1.5e-10, (inner, i)
 
 
 def test_pool_rejects_what_can_never_fit_and_unknown_ids(env):

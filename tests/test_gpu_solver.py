@@ -84,15 +84,20 @@ def test_multi_rhs_solve_matches_single(setup):
         assert np.array_equal(xs[j], x1), f"rhs {j} differs between batched and alone"
 
 
-def test_graph_replay_matches_eager(setup):
+@pytest.mark.parametrize("inner", [0, 1, 2, 3])
+def test_graph_replay_matches_eager_and_oracle(setup, inner):
     q, a, U, b, x_ref, D = setup
-    rc0, st0, x0 = _solve(q, D, b, 1, use_graph=0, check_every=5)
-    rc1, st1, x1 = _solve(q, D, b, 1, use_graph=1, check_every=5)
+    rc0, st0, x0 = _solve(q, D, b, inner, use_graph=0, check_every=5)
+    rc1, st1, x1 = _solve(q, D, b, inner, use_graph=1, check_every=5)
     assert rc0 == rc1 == q.QDWF_OK
     assert st0.iterations == st1.iterations
     assert np.array_equal(x0, x1)
+    # the replayed solve against the oracle: its CG solution and its operator
+    assert _rel(x1, x_ref) <= 1e-8
+    r = b - cpu.mpc(a, U, cpu.mpc(a, U, x1), dagger=True)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.5e-10
     # a second solve reuses nothing stale
-    rc2, st2, x2 = _solve(q, D, b, 1, use_graph=1, check_every=5)
+    rc2, st2, x2 = _solve(q, D, b, inner, use_graph=1, check_every=5)
     assert np.array_equal(x1, x2)
 
 
