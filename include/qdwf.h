@@ -267,6 +267,21 @@ int qdwf_triad(void* a, const void* b, const void* c, double s, int64_t n, int p
 int qdwf_dot(qdwf_ctx* ctx, double* out, const void* x, const void* y, int subset, int prec,
              int layout, int nrhs, void* ws, void* stream);
 
+/* qdwf_dot for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and the same results, bit for bit, with the partial sums in a
+ * static device array of QDWF_NOALLOC_SCRATCH_BYTES per GPU (held until the
+ * process ends) instead of a workspace. The call allocates nothing. It
+ * returns QDWF_EINVAL, launching nothing, when the reduction needs more
+ * scratch than that (qdwf_workspace_bytes(ctx, QDWF_OP_REDUCE, prec, nrhs)
+ * bytes; up to 32 right-hand sides fit for any field size). Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (other threads,
+ * other streams) race and must be serialised by the caller. The first call
+ * on a device looks up the array's device address. Synchronises `stream`. */
+#define QDWF_NOALLOC_SCRATCH_BYTES 540672
+int qdwf_dot_noalloc(qdwf_ctx* ctx, double* out, const void* x, const void* y, int subset,
+                     int prec, int layout, int nrhs, void* stream);
+
 /* ---- solver ----------------------------------------------------------- */
 /* Solves for nrhs right-hand sides at once (links loaded once per tile for
  * all of them). x, b are FP64 fields in params->layout: odd half fields for

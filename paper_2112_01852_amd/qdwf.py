@@ -22,6 +22,7 @@ QDWF_EVEN, QDWF_ODD, QDWF_FULL = 0, 1, 2
 QDWF_MEE_FWD, QDWF_MEE_INV = 0, 1
 QDWF_SYS_NORMAL_PC, QDWF_SYS_FULL = 0, 1
 QDWF_OP_MPC, QDWF_OP_MDAGM, QDWF_OP_SOLVE, QDWF_OP_REDUCE, QDWF_OP_TUNE = 0, 1, 2, 3, 4
+QDWF_NOALLOC_SCRATCH_BYTES = 540672   # static scratch of qdwf_dot_noalloc per GPU
 
 TORCH_DTYPE = {QDWF_F64: torch.float64, QDWF_F32: torch.float32,
                QDWF_F16: torch.float16, QDWF_BF16: torch.bfloat16}
@@ -87,6 +88,7 @@ _SIG = {
     "qdwf_apply_MdagM": ([_P, _P, _P, _I, _I, _I, _P, _P], _I),
     "qdwf_workspace_bytes": ([_P, _I, _I, _I], ctypes.c_size_t),
     "qdwf_dot": ([_P, _P, _P, _P, _I, _I, _I, _I, _P, _P], _I),
+    "qdwf_dot_noalloc": ([_P, _P, _P, _P, _I, _I, _I, _I, _P], _I),
     "qdwf_solve": ([_P, _P, _P, _I, ctypes.POINTER(qdwf_solve_params),
                     ctypes.POINTER(qdwf_solve_stats), _P, _P], _I),
     "qdwf_geometry_tables": ([_P, _P, _P, _P], _I),
@@ -275,6 +277,14 @@ def qdwf_dot(ctx, x, y, subset, prec, layout, nrhs, ws, stream=None):
     _check(lib().qdwf_dot(ctx, ctypes.cast(out, ctypes.c_void_p), _ptr(x, "x"), _ptr(y, "y"),
                           int(subset), int(prec), int(layout), int(nrhs), _ptr(ws, "ws"),
                           _stream(stream)))
+    return [complex(out[2 * i], out[2 * i + 1]) for i in range(int(nrhs))]
+
+
+def qdwf_dot_noalloc(ctx, x, y, subset, prec, layout, nrhs, stream=None):
+    out = (ctypes.c_double * (2 * int(nrhs)))()
+    _check(lib().qdwf_dot_noalloc(ctx, ctypes.cast(out, ctypes.c_void_p), _ptr(x, "x"),
+                                  _ptr(y, "y"), int(subset), int(prec), int(layout), int(nrhs),
+                                  _stream(stream)))
     return [complex(out[2 * i], out[2 * i + 1]) for i in range(int(nrhs))]
 
 
