@@ -433,67 +433,164 @@ def multi_rhs_bench(args, torch, q, I):
 
 
 def serving_bench(args, torch, q):
-    """Poisson stream of mixed-precision even-odd Mobius solves through the
-    pool (volume 8^4..24^4, Ls 8/12/16, mf log-uniform [1e-3, 1e-1])."""
+    """Served stream of even-odd Mobius solves (volume 8^4..24^4, Ls 8/12/16,
+    mf log-uniform [1e-3, 1e-1], own smoothed links and Gaussian source each)
+    through the pool: continuous batching, grouped launches, admission by
+    arena footprint. First all requests at once (the pool's saturation
+    throughput), then Poisson arrivals at rho = 0.5, 0.9 and 1.2 of that
+    throughput. Baseline at every load: the same stream served first in,
+    first out by plain FP64 CG one request at a time (the same pool with one
+    slot and FP64 inner precision), a real run on the same GPU."""
     from paper_2112_01852_amd import serve
     n = args.serve_requests
     specs = serve.make_specs(n, 5000)
-    prepared = serve.prepare(specs)
+    t0 = time.time()
+    prepared = serve.prepare(specs, with_x=False)
+    log(f"serving: {n} requests prepared in {time.time() - t0:.1f}s")
     prm_mixed = q.solve_params(inner_prec=q.QDWF_F16, layout=q.QDWF_RIRI, tol=1e-10,
-                               check_every=8, use_graph=0)
+                               check_every=8)
     prm_plain = q.solve_params(inner_prec=q.QDWF_F64, layout=q.QDWF_RIRI, tol=1e-10,
-                               check_every=8, use_graph=1)
-    # isolated service times (plain FP64) give the offered load and the FIFO baseline
-    t_plain = []
-    for p in prepared:
-        rc, st, dt, _ = serve.solo_solve(p, prm_plain)
-        t_plain.append(dt)
-    mean_s = float(np.mean(t_plain))
-    rate = args.serve_load / mean_s
-    arrivals = serve.poisson_arrivals(n, rate, 5001)
-    budget = int(args.serve_budget_gb * 2**30)
-    res = serve.run_pool(prepared, arrivals, prm_mixed, budget, max_slots=8)
-    base_lat, base_end = serve.fifo_baseline(t_plain, arrivals)
-    ok = sum(1 for s in res["status"] if s == q.QDWF_OK)
-    out = {"requests": n, "offered_load_vs_fp64": args.serve_load, "arrival_rate_per_s": rate,
-           "budget_bytes": budget, "peak_bytes": res["peak_bytes"], "converged": ok,
-           "served_mixed": {**serve.percentiles(res["latency"]),
-                            "solves_per_s": n / res["makespan"]},
-           "fifo_plain_fp64": {**serve.percentiles(base_lat), "solves_per_s": n / base_end,
-                               "mean_service_s": mean_s}}
-    log("serving", out)
+                               check_every=8)
+    arena = int(args.serve_budget_gb * 2**30)
+    slots = 64
+
+    def summary(res):
+        ok = sum(1 for s_ in res["status"] if s_ == q.QDWF_OK)
+        worst = max(st["true_residual"] for st in res["stats"])
+        return {**serve.percentiles(res["latency"]), "solves_per_s": n / res["makespan"],
+                "makespan_s": res["makespan"], "converged": ok, "worst_true_residual": worst,
+                "peak_arena_bytes": res["peak_bytes"]}
+
+    sat = serve.run_pool(prepared, np.zeros(n), prm_mixed, arena, slots, keep_x=False)
+    rate = n / sat["makespan"]
+    out = {"requests": n, "arena_bytes": arena, "max_slots": slots,
+           "mixed_inner": "f16", "check_every": 8,
+           "saturation_mixed": summary(sat)}
+    log("serving saturation", out["saturation_mixed"])
+    loads = {}
+    for rho in args.serve_loads:
+        arr = serve.poisson_arrivals(n, rho * rate, 5001)
+        mixed = summary(serve.run_pool(prepared, arr, prm_mixed, arena, slots, keep_x=False))
+        log(f"serving rho={rho} mixed", mixed)
+        fifo = summary(serve.run_pool(prepared, arr, prm_plain, arena, 1, keep_x=False))
+        log(f"serving rho={rho} fifo fp64", fifo)
+        loads[f"rho_{rho}"] = {"arrival_rate_per_s": rho * rate, "served_mixed": mixed,
+                               "fifo_plain_fp64": fifo}
+    out["loads"] = loads
+    out["offered_load_basis"] = ("rho times the mixed pool's saturation throughput "
+                                 "(all requests submitted at once)")
+    del prepared
+    torch.cuda.empty_cache()
     return out
 
 
-def cpu_baseline(min_seconds=10.0, max_reps=4):
-    """FP64 oracle (plain C++ loops, OpenMP) applying the benchmark's operator
-    to the benchmark's own 32^4 x 16 lattice and inputs (same seeds), repeated
-    until about min_seconds of CPU work have been timed."""
+def _omp_set_threads(n):
+    """Thread count of the oracle's OpenMP regions from here on (libgomp, the
+    runtime the oracle is built against)."""
+    import ctypes
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(fp64_cg_iterations=None, min_seconds=10.0, max_reps=4):
+    """The FP64 oracle (plain C++ loops, OpenMP) timed on the host cores, on
+    bounded samples of the benchmark's workloads (same seeds):
+      * D at 32^4 x 16 (the headline workload), all cores;
+      * D at 4^4 x 8 Shamir FP64 (the small parity workload), 1 thread and
+        all cores;
+      * D at 16^4 x 16 Mobius, 1 thread (32^4 x 16 at one thread would take
+        a minute; the per-site rate is what is compared);
+      * the normal-equation CG at 24^4 x 16 (smoothed links, mf 0.01), all
+        cores: time per iteration from 3 iterations (each iteration, and the
+        closing residual, is one M_pc^dag M_pc), extrapolated to the
+        iteration count of the FP64 solve on the GPU (labelled as such).
+    `value` is the first leg, in the headline's unit (GFlop/s, 1320 flops per
+    5D site per hop)."""
     from oracle import cpu
     from paper_2112_01852_amd import inputs as I
     cpu.build(force=False)
-    L, Ls = (32, 32, 32, 32), 16
-    a = cpu.Action(L=L, Ls=Ls, **MOBIUS)
-    U = I.gauge_field(L, "haar", 2000)
-    psi = I.gaussian_spinor(L, Ls, 2001)
-    reps, dt = 0, 0.0
-    while reps < max_reps and (reps == 0 or dt < min_seconds):
-        t0 = time.time()
-        out = cpu.dwf(a, U, psi)
-        dt += time.time() - t0
-        reps += 1
-        del out
-    sites = a.V * Ls
     try:
         cores = len(os.sched_getaffinity(0))
     except Exception:
         cores = os.cpu_count()
-    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
-    return {"value": FLOPS_PER_SITE * sites * reps / dt / 1e9, "unit": "GFlop/s",
-            "cores": min(cores, threads), "kind": "oracle", "seconds": dt,
+    threads = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+
+    def time_D(a, U, psi, n_threads, min_s, max_r):
+        _omp_set_threads(n_threads)
+        reps, dt = 0, 0.0
+        while reps < max_r and (reps == 0 or dt < min_s):
+            t0 = time.time()
+            out = cpu.dwf(a, U, psi)
+            dt += time.time() - t0
+            reps += 1
+            del out
+        sites = a.V * a.Ls
+        return {"gflops": FLOPS_PER_SITE * sites * reps / dt / 1e9, "seconds": dt,
+                "applications": reps, "threads": n_threads, "sites_5d": sites}
+
+    legs = {}
+    L, Ls = (32, 32, 32, 32), 16
+    a = cpu.Action(L=L, Ls=Ls, **MOBIUS)
+    U = I.gauge_field(L, "haar", 2000)
+    psi = I.gaussian_spinor(L, Ls, 2001)
+    legs["D_mobius_32x32x32x32x16_all_cores"] = time_D(a, U, psi, threads, min_seconds, max_reps)
+    del U, psi
+    log("cpu D 32^4", legs["D_mobius_32x32x32x32x16_all_cores"])
+    L, Ls = (4, 4, 4, 4), 8
+    a = cpu.Action(L=L, Ls=Ls, M5=1.8, mf=0.01, b=1.0, c=0.0)
+    U = I.gauge_field(L, "haar", 1000)
+    psi = I.gaussian_spinor(L, Ls, 1001)
+    legs["D_shamir_4x4x4x4x8_1_thread"] = time_D(a, U, psi, 1, 1.0, 2000)
+    legs["D_shamir_4x4x4x4x8_all_cores"] = time_D(a, U, psi, threads, 1.0, 2000)
+    L, Ls = (16, 16, 16, 16), 16
+    a = cpu.Action(L=L, Ls=Ls, **MOBIUS)
+    U = I.gauge_field(L, "haar", 2000)
+    psi = I.gaussian_spinor(L, Ls, 2001)
+    legs["D_mobius_16x16x16x16x16_1_thread"] = time_D(a, U, psi, 1, 2.0, 3)
+    del U, psi
+    log("cpu D small", {k: v for k, v in legs.items() if "32x32" not in k})
+    # normal-equation CG at 24^4 x 16: time per iteration
+    _omp_set_threads(threads)
+    L, Ls = (24, 24, 24, 24), 16
+    a = cpu.Action(L=L, Ls=Ls, **MOBIUS)
+    U = I.gauge_field(L, "smooth", 3000, eps=0.3)
+    b = cpu.restrict(I.gaussian_spinor(L, Ls, 3001), L, 1)
+    k = 3
+    t0 = time.time()
+    x, it, res = cpu.cg(a, U, b, tol=1e-10, max_iter=k)
+    dt = time.time() - t0
+    per_it = dt / (it + 1)
+    cg = {"threads": threads, "sample_iterations": it, "sample_seconds": dt,
+          "seconds_per_iteration": per_it,
+          "gflops": FLOPS_PER_SITE * 4 * a.V // 2 * Ls / per_it / 1e9}
+    if fp64_cg_iterations:
+        cg["iterations"] = int(fp64_cg_iterations)
+        cg["solve_seconds_extrapolated"] = per_it * (int(fp64_cg_iterations) + 1)
+        cg["solves_per_s_extrapolated"] = 1.0 / cg["solve_seconds_extrapolated"]
+        cg["extrapolated_from"] = ("seconds per iteration of the oracle CG times the iteration "
+                                   "count of the FP64 CG on the GPU (same system, same tol)")
+    legs["cg_normal_pc_24x24x24x24x16_all_cores"] = cg
+    del U, b, x
+    _omp_set_threads(threads)
+    log("cpu cg", cg)
+    head = legs["D_mobius_32x32x32x32x16_all_cores"]
+    return {"value": head["gflops"], "unit": "GFlop/s", "cores": threads, "kind": "oracle",
+            "seconds": head["seconds"], "cpu_model": _cpu_model(), "host_cores": cores,
             "sample": f"FP64 oracle D_dwf (Mobius b=1.5 c=0.5) on the full 32^4 x Ls16 lattice "
-                      f"with the benchmark's inputs, {reps} application(s); GFlop/s with 1320 "
-                      f"flops per 5D site"}
+                      f"with the benchmark's inputs, {head['applications']} application(s) on "
+                      f"{threads} threads; GFlop/s with 1320 flops per 5D site. Further legs "
+                      f"(1 thread, 4^4 x 8, 16^4 x 16, CG at 24^4 x 16) under 'legs'",
+            "legs": legs}
 
 
 def main():
@@ -507,11 +604,12 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-paper", action="store_true",
                     help="skip the Table 1 / Table 2 volumes and the streaming probes")
-    ap.add_argument("--serve-requests", type=int, default=24)
-    ap.add_argument("--serve-load", type=float, default=0.9,
-                    help="offered load relative to one-at-a-time plain FP64 service")
-    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
-    ap.add_argument("--only", choices=["solver", "wilson"], default=None,
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-loads", type=lambda v: [float(x) for x in v.split(",")],
+                    default=[0.5, 0.9, 1.2],
+                    help="offered loads relative to the mixed pool's saturation throughput")
+    ap.add_argument("--serve-budget-gb", type=float, default=48.0)
+    ap.add_argument("--only", choices=["solver", "wilson", "serving"], default=None,
                     help="run only this row and print its JSON object (for profiling)")
     ap.add_argument("--inner", default="",
                     help="comma list of solver inner precisions (f64,f32,f16,bf16; default all)")
@@ -527,7 +625,12 @@ def main():
     from paper_2112_01852_amd import inputs as I
     q.lib()
     if args.only == "solver":
-        print(json.dumps({"solver_24x24x24x24x16": solver_bench(args, torch, q, I)}), flush=True)
+        probe = copy_probe(torch)   # also the counters' calibration copy
+        print(json.dumps({"attainable_hbm": probe,
+                          "solver_24x24x24x24x16": solver_bench(args, torch, q, I)}), flush=True)
+        return
+    if args.only == "serving":
+        print(json.dumps({"serving": serving_bench(args, torch, q)}), flush=True)
         return
     if args.only == "wilson":
         probe = copy_probe(torch)   # also the counters' calibration copy
@@ -548,7 +651,10 @@ def main():
     solver = None if args.no_solver else solver_bench(args, torch, q, I)
     multi = None if args.no_multi else multi_rhs_bench(args, torch, q, I)
     served = None if args.no_serve else serving_bench(args, torch, q)
-    cpub = None if args.no_cpu else cpu_baseline()
+    fp64_its = None
+    if solver and solver.get("f64"):
+        fp64_its = solver["f64"]["iterations"]
+    cpub = None if args.no_cpu else cpu_baseline(fp64_its)
     line = {
         "metric": "Dslash GFlop/s+HBM GB/s (32^4xLs16); mixed-prec CG solves/s, p50/p99 latency",
         "value": head["gflops"],

@@ -313,39 +313,64 @@ int qdwf_tuned_shape(qdwf_ctx* ctx, int prec, int layout, int dagger, int nrhs, 
 /* ---- serving pool ----------------------------------------------------- */
 /* Continuous batching of independent solves of M_pc^dag M_pc x_o = b_o, each
  * with its own lattice, action, gauge field and source. Requests wait in FIFO
- * order until their device footprint (qdwf_request_bytes) fits the pool's
- * HBM budget and one of max_slots slots is free; admitted requests each run
- * on their slot's stream and advance by one round (check_every inner
- * iterations, or a reliable update) per qdwf_pool_step, with every round of
- * a step launched before any is waited for, so requests overlap on the
- * device. A request's result does not depend on what else is in the pool.
- * Admission and retirement allocate and free the request's device memory. */
+ * order until their device memory (qdwf_request_bytes) fits the caller's
+ * arena and one of max_slots slots is free. All admitted requests advance
+ * together: each qdwf_pool_step replays one round -- check_every repetitions
+ * of [the reliable updates that are due; one CG iteration] -- in which every
+ * step of the iteration is a single launch covering all of them (kernels walk
+ * a device table of the requests' arguments), captured as a HIP graph when
+ * the pool is created. A request's result does not depend on what else is
+ * in the pool: its arithmetic is that of qdwf_solve on one right-hand side
+ * with the same parameters.
+ *
+ * Memory: the caller owns the arena (device memory, 256-byte aligned, kept
+ * valid until qdwf_pool_destroy); the pool sub-allocates it for its own table
+ * and states (qdwf_pool_overhead_bytes), for each admitted request's links,
+ * matrices, vectors and workspace, and for the site tables of each lattice
+ * shape (shared by the requests of that shape, kept while room allows). After
+ * qdwf_pool_create the pool allocates no device memory; it holds pinned host
+ * staging allocated at creation. Not thread-safe per pool. */
 typedef struct qdwf_pool qdwf_pool;
 
 typedef struct {
-  qdwf_action act;            /* lattice and action of this solve                   */
+  qdwf_action act;            /* lattice and action; 8 <= Ls <= 32                  */
   const void* U;              /* canonical gauge field, complex128, device          */
   const void* b;              /* canonical source, complex128, device; odd sites used */
   void* x_out;                /* canonical complex128 device buffer; odd sites are  */
                               /* written when the request finishes                   */
-  qdwf_solve_params params;   /* system is taken as QDWF_SYS_NORMAL_PC; x0 = 0      */
+  qdwf_solve_params params;   /* tol, delta, max_iter per request; inner_prec and    */
+                              /* layout must be the pool's; system NORMAL_PC, x0 = 0 */
 } qdwf_request;               /* U, b, x_out must stay valid until the request ends */
 
-/* Device bytes a request occupies while admitted. */
+/* Arena bytes a request occupies while admitted, counting its lattice shape's
+ * site tables (shared with other admitted requests of that shape). */
 size_t qdwf_request_bytes(const qdwf_action* act, const qdwf_solve_params* params);
-int qdwf_pool_create(int device, size_t hbm_budget, int max_slots, qdwf_pool** out);
+/* Arena bytes the pool keeps for itself (0 for max_slots out of range). */
+size_t qdwf_pool_overhead_bytes(int max_slots);
+/* params: inner_prec and layout of every request, check_every = iterations
+ * per round (1..64; default 8 if <= 0). max_slots in [1, 64]. The arena's
+ * size is the pool's budget; creation fails with QDWF_EINVAL if it is smaller
+ * than qdwf_pool_overhead_bytes(max_slots). */
+int qdwf_pool_create(int device, void* arena, size_t arena_bytes, int max_slots,
+                     const qdwf_solve_params* params, qdwf_pool** out);
+/* Waits for the round in flight, then frees the pool (not the arena). */
 int qdwf_pool_destroy(qdwf_pool* pool);
-/* Queues a request (never blocks); QDWF_EINVAL if it can never fit the budget. */
+/* Queues a request (never blocks); QDWF_EINVAL if it can never fit the arena
+ * or its parameters do not match the pool. */
 int qdwf_pool_submit(qdwf_pool* pool, const qdwf_request* req, uint64_t* id);
-/* One scheduling step: advance every admitted request by one round, admit
- * queued requests that fit, retire finished ones. *n_active (may be NULL)
- * receives the number of requests still admitted. */
-int qdwf_pool_step(qdwf_pool* pool, int* n_active);
+/* One scheduling step on `stream` (a hipStream_t, NULL = default): waits for
+ * the previous round, retires the requests it finished (their x_out written
+ * by work queued on `stream`), admits queued requests that fit, and queues
+ * the next round for all admitted requests. *n_active (may be NULL) receives
+ * the number of requests admitted after the step. */
+int qdwf_pool_step(qdwf_pool* pool, void* stream, int* n_active);
 /* QDWF_EBUSY while the request is queued or running; otherwise its solve
  * status (QDWF_OK, QDWF_ENOTCONV, QDWF_ENAN, ...) with stats filled, after
- * which the id is forgotten. */
+ * which the id is forgotten. A finished request's x_out is complete once the
+ * work queued on the step's stream has run. */
 int qdwf_pool_poll(qdwf_pool* pool, uint64_t id, qdwf_solve_stats* stats);
-/* Bytes admitted now and at peak, and the numbers of admitted and queued requests. */
+/* Arena bytes in use now and at peak (including the pool's own), and the
+ * numbers of admitted and queued requests. */
 int qdwf_pool_info(qdwf_pool* pool, size_t* in_use, size_t* peak, int* n_active, int* n_queued);
 
 /* ---- geometry (tests) ------------------------------------------------- */

@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libqdwf.so")
 ARCH = os.environ.get("QDWF_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "hop.hip", "pack.hip", "local.hip", "solver.hip", "tune.cpp", "pool.cpp", "wilson.hip", "stream.hip", "halo.hip", "sweep.hip", "noalloc.hip"]
+SOURCES = ["api.cpp", "hop.hip", "pack.hip", "local.hip", "solver.hip", "tune.cpp", "pool.cpp", "wilson.hip", "stream.hip", "halo.hip", "sweep.hip", "noalloc.hip", "group.hip"]
 
 # Packed-FP32 instructions are switched off for all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

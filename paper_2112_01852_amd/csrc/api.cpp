@@ -41,10 +41,171 @@ int fail(int code, const char* fmt, ...) {
 
 std::vector<double> build_local_matrices(const qdwf_action& a);
 
-size_t ctx_bytes(const qdwf_action& a) {
-  const size_t V = (size_t)a.L[0] * a.L[1] * a.L[2] * a.L[3], Vh = V / 2;
-  const size_t mats = (size_t)MAT_COUNT * 2 * a.Ls * a.Ls * (8 + 4);
-  return 2 * 8 * Vh * 4 + 2 * Vh * 4 + 2 * 4 * Vh * 18 * (8 + 4 + 2 + 2) + mats + 8 * 256;
+CtxLayout ctx_layout(const qdwf_action& a, bool with_geom, unsigned link_mask, bool derived) {
+  Geom g;
+  for (int mu = 0; mu < 4; ++mu) g.L[mu] = a.L[mu];
+  g.Ls = a.Ls;
+  g.V = a.L[0] * a.L[1] * a.L[2] * a.L[3];
+  g.Vh = g.V / 2;
+  g.n5h = (long)g.Vh * g.Ls;
+  const size_t Vh = (size_t)g.Vh, V = (size_t)g.V;
+  const size_t none = SIZE_MAX;
+  CtxLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += (bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  L.nbr = L.site_lex = L.idx = none;
+  if (with_geom) {
+    L.nbr = take(sizeof(int32_t) * 2 * 8 * Vh);
+    L.site_lex = take(sizeof(int32_t) * 2 * Vh);
+    L.idx = take(sizeof(int32_t) * V);
+  }
+  L.geom_bytes = o;
+  const size_t mats = (size_t)MAT_COUNT * 2 * a.Ls * a.Ls;
+  L.mat64 = take(sizeof(double) * mats);
+  L.mat32 = take(sizeof(float) * mats);
+  const size_t link_reals = (size_t)2 * 4 * Vh * 18;
+  for (int p = 0; p < 4; ++p) {
+    L.links[p] = (link_mask >> p & 1u) ? take(link_reals * prec_bytes(p)) : none;
+    L.dlinks[p] = L.wlinks[p] = none;
+  }
+  if (derived && sweep_geometry(g))
+    for (int p = QDWF_F32; p <= QDWF_BF16; ++p)
+      if (link_mask >> p & 1u) L.dlinks[p] = take(2 * link_reals * prec_bytes(p));
+  if (derived && g.Ls == 1)   // FP64 and FP32: measured slower with 16-bit storage
+    for (int p = QDWF_F64; p <= QDWF_F32; ++p)
+      if (link_mask >> p & 1u) L.wlinks[p] = take((size_t)2 * 4 * 18 * Vh * prec_bytes(p));
+  L.total = o;
+  return L;
+}
+
+size_t ctx_bytes(const qdwf_action& a) { return ctx_layout(a, true, 0xFu, true).total; }
+
+void place_arrays(qdwf_ctx* c, char* base, const CtxLayout& lay) {
+  auto at = [&](size_t off) -> void* { return off == SIZE_MAX ? nullptr : base + off; };
+  if (lay.nbr != SIZE_MAX) {
+    c->d_nbr = reinterpret_cast<int32_t*>(at(lay.nbr));
+    c->d_site_lex = reinterpret_cast<int32_t*>(at(lay.site_lex));
+    c->d_idx = reinterpret_cast<int32_t*>(at(lay.idx));
+  }
+  c->d_mat64 = reinterpret_cast<double*>(at(lay.mat64));
+  c->d_mat32 = reinterpret_cast<float*>(at(lay.mat32));
+  for (int p = 0; p < 4; ++p) {
+    c->d_links[p] = at(lay.links[p]);
+    c->d_dlinks[p] = at(lay.dlinks[p]);
+    c->d_wlinks[p] = at(lay.wlinks[p]);
+  }
+}
+
+hipError_t upload_tables(qdwf_ctx* c, bool with_geom) {
+  hipError_t e = hipSuccess;
+  const GeomTables& G = *c->geo;
+  if (with_geom) {
+    e = hipMemcpy(c->d_nbr, G.nbr.data(), sizeof(int32_t) * G.nbr.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(c->d_site_lex, G.site_lex.data(), sizeof(int32_t) * G.site_lex.size(),
+                    hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(c->d_idx, G.idx.data(), sizeof(int32_t) * G.idx.size(), hipMemcpyHostToDevice);
+  }
+  const std::vector<float> m32(c->h_mat.begin(), c->h_mat.end());
+  if (e == hipSuccess)
+    e = hipMemcpy(c->d_mat64, c->h_mat.data(), sizeof(double) * c->h_mat.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(c->d_mat32, m32.data(), sizeof(float) * m32.size(), hipMemcpyHostToDevice);
+  return e;
+}
+
+std::shared_ptr<const GeomTables> build_geometry(const int L[4], const int bc[4]) {
+  auto G = std::make_shared<GeomTables>();
+  const int V = L[0] * L[1] * L[2] * L[3], Vh = V / 2;
+  for (int mu = 0; mu < 4; ++mu) { G->L[mu] = L[mu]; G->bc[mu] = bc[mu]; }
+  // Internal site order of each parity. The lattice is cut into 8 slabs
+  // along the split dimension, one per XCD (blocks of consecutive internal
+  // sites reach the XCDs in contiguous ranges); inside a slab, tiles over the
+  // other three dimensions are swept along the sweep dimension. The sites a
+  // XCD works on at any moment then form a compact 4D region whose
+  // neighbours are still in its L2, and all XCDs advance along the sweep
+  // together, so neighbours shared across XCDs meet in the last-level cache.
+  // Defaults: split z, sweep t, (x, y, z) tile 32 x 4 x Lz/8. Overrides:
+  // QDWF_ORDER="split,sweep" (dimension numbers 0..3 = x, y, z, t) and
+  // QDWF_TILE="tx,ty,tz[,tt]" (the entry of the sweep dimension is ignored).
+  int sd = 2, wd = 3;
+  if (const char* e = std::getenv("QDWF_ORDER")) {
+    int a = -1, b = -1;
+    if (std::sscanf(e, "%d,%d", &a, &b) == 2 && a >= 0 && a < 4 && b >= 0 && b < 4 && a != b) {
+      sd = a; wd = b;
+    }
+  }
+  int tile[4] = {std::min(L[0], 32), std::min(L[1], 4), std::max(1, L[2] / 8), 1};
+  if (sd != 2 || wd != 3) {
+    for (int mu = 0; mu < 4; ++mu) tile[mu] = std::min(L[mu], 4);
+    tile[sd] = std::max(1, L[sd] / 8);
+  }
+  if (const char* e = std::getenv("QDWF_TILE")) {
+    int t4[4] = {0, 0, 0, 1};
+    const int n = std::sscanf(e, "%d,%d,%d,%d", &t4[0], &t4[1], &t4[2], &t4[3]);
+    if (n >= 3 && t4[0] > 0 && t4[1] > 0 && t4[2] > 0 && t4[3] > 0)
+      for (int mu = 0; mu < 4; ++mu) tile[mu] = t4[mu];
+  }
+  tile[wd] = 1;
+  for (int k = 0; k < 4; ++k) G->tile[k] = tile[k];
+  G->order[0] = sd;
+  G->order[1] = wd;
+  std::vector<int64_t> key(V);
+  for (int lex = 0; lex < V; ++lex) {
+    int x[4], r = lex;
+    for (int mu = 0; mu < 4; ++mu) { x[mu] = r % L[mu]; r /= L[mu]; }
+    int64_t k = (x[sd] * 8) / L[sd];
+    for (int mu = 3; mu >= 0; --mu)
+      if (mu != wd) k = k * L[mu] + x[mu] / tile[mu];
+    k = k * L[wd] + x[wd];
+    for (int mu = 3; mu >= 0; --mu)
+      if (mu != wd) k = k * L[mu] + x[mu] % tile[mu];
+    key[lex] = k;
+  }
+  G->site_lex.assign((size_t)2 * Vh, 0);
+  G->idx.assign((size_t)V, 0);
+  {
+    std::vector<int> order(V);
+    for (int i = 0; i < V; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
+    int cnt[2] = {0, 0};
+    for (int lex : order) {
+      int x[4], r = lex;
+      for (int mu = 0; mu < 4; ++mu) { x[mu] = r % L[mu]; r /= L[mu]; }
+      const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+      const int i = cnt[p]++;
+      G->site_lex[(size_t)p * Vh + i] = lex;
+      G->idx[lex] = i;
+    }
+  }
+  // neighbour and boundary tables in the internal order
+  G->nbr.assign((size_t)2 * 8 * Vh, 0);
+  G->sign.assign((size_t)2 * 8 * Vh, 0);
+  for (int lex = 0; lex < V; ++lex) {
+    int x[4], r = lex;
+    for (int mu = 0; mu < 4; ++mu) { x[mu] = r % L[mu]; r /= L[mu]; }
+    const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
+    const int i = G->idx[lex];
+    for (int d = 0; d < 8; ++d) {
+      const int mu = d & 3;
+      int y[4] = {x[0], x[1], x[2], x[3]};
+      int sg = 1;
+      if (d < 4) {
+        if (++y[mu] == L[mu]) { y[mu] = 0; sg = bc[mu]; }
+      } else {
+        if (--y[mu] < 0) { y[mu] = L[mu] - 1; sg = bc[mu]; }
+      }
+      const int yl = ((y[3] * L[2] + y[2]) * L[1] + y[1]) * L[0] + y[0];
+      G->nbr[((size_t)p * 8 + d) * Vh + i] = G->idx[yl];
+      G->sign[((size_t)p * 8 + d) * Vh + i] = (int8_t)sg;
+    }
+  }
+  return G;
 }
 
 }  // namespace qdwf
@@ -139,122 +300,30 @@ int qdwf_create(const qdwf_action* act, int device, qdwf_ctx** out) {
   g.V = act->L[0] * act->L[1] * act->L[2] * act->L[3];
   g.Vh = g.V / 2;
   g.n5h = (long)g.Vh * g.Ls;
-
-  // Internal site order of each parity. The lattice is cut into 8 slabs
-  // along the split dimension, one per XCD (blocks of consecutive internal
-  // sites reach the XCDs in contiguous ranges); inside a slab, tiles over the
-  // other three dimensions are swept along the sweep dimension. The sites a
-  // XCD works on at any moment then form a compact 4D region whose
-  // neighbours are still in its L2, and all XCDs advance along the sweep
-  // together, so neighbours shared across XCDs meet in the last-level cache.
-  // Defaults: split z, sweep t, (x, y, z) tile 32 x 4 x Lz/8. Overrides:
-  // QDWF_ORDER="split,sweep" (dimension numbers 0..3 = x, y, z, t) and
-  // QDWF_TILE="tx,ty,tz[,tt]" (the entry of the sweep dimension is ignored).
-  const int* L = g.L;
-  int sd = 2, wd = 3;
-  if (const char* e = std::getenv("QDWF_ORDER")) {
-    int a = -1, b = -1;
-    if (std::sscanf(e, "%d,%d", &a, &b) == 2 && a >= 0 && a < 4 && b >= 0 && b < 4 && a != b) {
-      sd = a; wd = b;
-    }
+  try {
+    c->geo = build_geometry(act->L, act->bc);
+    c->h_mat = build_local_matrices(*act);
+  } catch (const std::bad_alloc&) {
+    delete c;
+    return fail(QDWF_ENOMEM, "host allocation of the site tables failed");
   }
-  int tile[4] = {std::min(L[0], 32), std::min(L[1], 4), std::max(1, L[2] / 8), 1};
-  if (sd != 2 || wd != 3) {
-    for (int mu = 0; mu < 4; ++mu) tile[mu] = std::min(L[mu], 4);
-    tile[sd] = std::max(1, L[sd] / 8);
-  }
-  if (const char* e = std::getenv("QDWF_TILE")) {
-    int t4[4] = {0, 0, 0, 1};
-    const int n = std::sscanf(e, "%d,%d,%d,%d", &t4[0], &t4[1], &t4[2], &t4[3]);
-    if (n >= 3 && t4[0] > 0 && t4[1] > 0 && t4[2] > 0 && t4[3] > 0)
-      for (int mu = 0; mu < 4; ++mu) tile[mu] = t4[mu];
-  }
-  tile[wd] = 1;
-  for (int k = 0; k < 4; ++k) c->tile[k] = tile[k];
-  c->order[0] = sd;
-  c->order[1] = wd;
-  std::vector<int64_t> key(g.V);
-  for (int lex = 0; lex < g.V; ++lex) {
-    int x[4], r = lex;
-    for (int mu = 0; mu < 4; ++mu) { x[mu] = r % L[mu]; r /= L[mu]; }
-    int64_t k = (x[sd] * 8) / L[sd];
-    for (int mu = 3; mu >= 0; --mu)
-      if (mu != wd) k = k * L[mu] + x[mu] / tile[mu];
-    k = k * L[wd] + x[wd];
-    for (int mu = 3; mu >= 0; --mu)
-      if (mu != wd) k = k * L[mu] + x[mu] % tile[mu];
-    key[lex] = k;
-  }
-  c->h_site_lex.assign((size_t)2 * g.Vh, 0);
-  c->h_idx.assign((size_t)g.V, 0);
-  {
-    std::vector<int> order(g.V);
-    for (int i = 0; i < g.V; ++i) order[i] = i;
-    std::sort(order.begin(), order.end(), [&](int a, int b) { return key[a] < key[b]; });
-    int cnt[2] = {0, 0};
-    for (int lex : order) {
-      int x[4], r = lex;
-      for (int mu = 0; mu < 4; ++mu) { x[mu] = r % L[mu]; r /= L[mu]; }
-      const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
-      const int i = cnt[p]++;
-      c->h_site_lex[(size_t)p * g.Vh + i] = lex;
-      c->h_idx[lex] = i;
-    }
-  }
-  // neighbour and boundary tables in the internal order
-  c->h_nbr.assign((size_t)2 * 8 * g.Vh, 0);
-  c->h_sign.assign((size_t)2 * 8 * g.Vh, 0);
-  for (int lex = 0; lex < g.V; ++lex) {
-    int x[4], r = lex;
-    for (int mu = 0; mu < 4; ++mu) { x[mu] = r % L[mu]; r /= L[mu]; }
-    const int p = (x[0] + x[1] + x[2] + x[3]) & 1;
-    const int i = c->h_idx[lex];
-    for (int d = 0; d < 8; ++d) {
-      const int mu = d & 3;
-      int y[4] = {x[0], x[1], x[2], x[3]};
-      int sg = 1;
-      if (d < 4) {
-        if (++y[mu] == L[mu]) { y[mu] = 0; sg = act->bc[mu]; }
-      } else {
-        if (--y[mu] < 0) { y[mu] = L[mu] - 1; sg = act->bc[mu]; }
-      }
-      const int yl = ((y[3] * L[2] + y[2]) * L[1] + y[1]) * L[0] + y[0];
-      c->h_nbr[((size_t)p * 8 + d) * g.Vh + i] = c->h_idx[yl];
-      c->h_sign[((size_t)p * 8 + d) * g.Vh + i] = (int8_t)sg;
-    }
-  }
-  c->h_mat = build_local_matrices(*act);
-  std::vector<float> m32(c->h_mat.begin(), c->h_mat.end());
-
-  size_t link_reals = (size_t)2 * 4 * g.Vh * 18;
-  hipError_t e = hipSuccess;
-  e = hipMalloc(&c->d_nbr, sizeof(int32_t) * c->h_nbr.size());
-  if (e == hipSuccess) e = hipMalloc(&c->d_site_lex, sizeof(int32_t) * c->h_site_lex.size());
-  if (e == hipSuccess)
-    e = hipMemcpy(c->d_site_lex, c->h_site_lex.data(), sizeof(int32_t) * c->h_site_lex.size(),
-                  hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMalloc(&c->d_mat64, sizeof(double) * c->h_mat.size());
-  if (e == hipSuccess) e = hipMalloc(&c->d_mat32, sizeof(float) * m32.size());
-  for (int p = 0; p < 4 && e == hipSuccess; ++p) e = hipMalloc(&c->d_links[p], link_reals * prec_bytes(p));
-  if (e == hipSuccess) e = hipMalloc(&c->d_idx, sizeof(int32_t) * c->h_idx.size());
-  if (e == hipSuccess)
-    e = hipMemcpy(c->d_idx, c->h_idx.data(), sizeof(int32_t) * c->h_idx.size(), hipMemcpyHostToDevice);
-  if (sweep_geometry(g))
-    for (int p = QDWF_F32; p <= QDWF_BF16 && e == hipSuccess; ++p)
-      e = hipMalloc(&c->d_dlinks[p], 2 * link_reals * prec_bytes(p));
-  if (g.Ls == 1)   // FP64 and FP32: measured slower with 16-bit storage
-    for (int p = QDWF_F64; p <= QDWF_F32 && e == hipSuccess; ++p)
-      e = hipMalloc(&c->d_wlinks[p], (size_t)2 * 4 * 18 * g.Vh * prec_bytes(p));
-  if (e == hipSuccess)
-    e = hipMemcpy(c->d_nbr, c->h_nbr.data(), sizeof(int32_t) * c->h_nbr.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(c->d_mat64, c->h_mat.data(), sizeof(double) * c->h_mat.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(c->d_mat32, m32.data(), sizeof(float) * m32.size(), hipMemcpyHostToDevice);
+  for (int k = 0; k < 4; ++k) c->tile[k] = c->geo->tile[k];
+  for (int k = 0; k < 2; ++k) c->order[k] = c->geo->order[k];
+  // one device block holds every array of the context (its size is ctx_bytes)
+  const CtxLayout lay = ctx_layout(*act, true, 0xFu, true);
+  hipError_t e = hipMalloc(&c->d_block, lay.total);
   if (e != hipSuccess) {
     const int code = (e == hipErrorOutOfMemory) ? QDWF_ENOMEM : QDWF_EDEVICE;
+    c->d_block = nullptr;
     qdwf_destroy(c);
-    return fail(code, "device allocation in qdwf_create failed: %s", hipGetErrorString(e));
+    return fail(code, "device allocation of %zu bytes in qdwf_create failed: %s", lay.total,
+                hipGetErrorString(e));
+  }
+  place_arrays(c, reinterpret_cast<char*>(c->d_block), lay);
+  e = upload_tables(c, true);
+  if (e != hipSuccess) {
+    qdwf_destroy(c);
+    return fail(QDWF_EDEVICE, "upload of the site tables failed: %s", hipGetErrorString(e));
   }
   *out = c;
   return QDWF_OK;
@@ -263,17 +332,9 @@ int qdwf_create(const qdwf_action* act, int device, qdwf_ctx** out) {
 int qdwf_destroy(qdwf_ctx* ctx) {
   if (!ctx) return QDWF_OK;
   forget_tuning(ctx);
+  forget_solver_state(ctx);
   DeviceGuard dg(ctx->device);
-  if (ctx->d_nbr) (void)hipFree(ctx->d_nbr);
-  if (ctx->d_site_lex) (void)hipFree(ctx->d_site_lex);
-  if (ctx->d_mat64) (void)hipFree(ctx->d_mat64);
-  if (ctx->d_mat32) (void)hipFree(ctx->d_mat32);
-  if (ctx->d_idx) (void)hipFree(ctx->d_idx);
-  for (int p = 0; p < 4; ++p) {
-    if (ctx->d_links[p]) (void)hipFree(ctx->d_links[p]);
-    if (ctx->d_dlinks[p]) (void)hipFree(ctx->d_dlinks[p]);
-    if (ctx->d_wlinks[p]) (void)hipFree(ctx->d_wlinks[p]);
-  }
+  if (ctx->d_block) (void)hipFree(ctx->d_block);
   delete ctx;
   return QDWF_OK;
 }
@@ -589,7 +650,7 @@ int qdwf_geometry_tables(qdwf_ctx* ctx, int32_t* cb_of_lex, int32_t* nbr, int8_t
   CTX_CHECK(ctx);
   const Geom& g = ctx->g;
   if (cb_of_lex)
-    for (int l = 0; l < g.V; ++l) cb_of_lex[l] = ctx->h_idx[l];
+    for (int l = 0; l < g.V; ++l) cb_of_lex[l] = ctx->geo->idx[l];
   // the kernels read [p][d][cb]; the exported order is [p][cb][d]
   if (nbr) {
     std::vector<int32_t> dev((size_t)2 * 8 * g.Vh);
@@ -604,7 +665,7 @@ int qdwf_geometry_tables(qdwf_ctx* ctx, int32_t* cb_of_lex, int32_t* nbr, int8_t
     for (int p = 0; p < 2; ++p)
       for (int cb = 0; cb < g.Vh; ++cb)
         for (int d = 0; d < 8; ++d)
-          sign[((size_t)p * g.Vh + cb) * 8 + d] = ctx->h_sign[((size_t)p * 8 + d) * g.Vh + cb];
+          sign[((size_t)p * g.Vh + cb) * 8 + d] = ctx->geo->sign[((size_t)p * 8 + d) * g.Vh + cb];
   return QDWF_OK;
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -111,15 +112,72 @@ struct HopShape {
 
 }  // namespace qdwf
 
+namespace qdwf {
+
+// Site tables of a lattice shape and boundary: the traversal order of each
+// parity and the neighbour table in that order, built on the host; shared by
+// every context of that shape (a serving pool keeps one per shape).
+struct GeomTables {
+  int L[4], bc[4];
+  int tile[4];                     // tile of the traversal order (1 on the sweep dimension)
+  int order[2];                    // split and sweep dimension of the traversal order
+  std::vector<int32_t> site_lex;   // [2][Vh] lex index of each internal site
+  std::vector<int32_t> idx;        // [V] internal index of each lex site
+  std::vector<int32_t> nbr;        // [2][8][Vh] internal index of each neighbour
+  std::vector<int8_t> sign;        // [2][8][Vh] boundary factor of each hop
+};
+// qdwf_solve's captured inner iterations and what they were captured for.
+struct SolveGraph {
+  hipGraphExec_t exec = nullptr;
+  const void* ws = nullptr;
+  int nrhs = 0, inner = -1, layout = -1, k = 0;
+  double delta2 = -1.0;
+};
+
+// Builds the tables (throws std::bad_alloc on host memory exhaustion).
+std::shared_ptr<const GeomTables> build_geometry(const int L[4], const int bc[4]);
+
+// Device arrays of a context, each on a 256-byte boundary of one block:
+// byte offsets, SIZE_MAX where absent. geom_bytes: the site tables, which come
+// first (nbr, site_lex, idx); the rest depends on the action.
+struct CtxLayout {
+  size_t nbr, site_lex, idx, mat64, mat32;
+  size_t links[4], dlinks[4], wlinks[4];
+  size_t geom_bytes, total;
+};
+// with_geom: the block holds the site tables; link_mask: bit p set for the
+// packed links of precision p; derived: the doubled links of the t-sweep and
+// the lane-major links of 4D contexts, where the geometry has them.
+CtxLayout ctx_layout(const qdwf_action& a, bool with_geom, unsigned link_mask, bool derived);
+
+}  // namespace qdwf
+struct qdwf_ctx;
+namespace qdwf {
+// Points the context's array members at the block `base` laid out by lay.
+void place_arrays(qdwf_ctx* c, char* base, const CtxLayout& lay);
+// Copies the site tables (with_geom) and the 5D-local matrices of c to the
+// device (synchronous copies; contexts of qdwf_create).
+hipError_t upload_tables(qdwf_ctx* c, bool with_geom);
+// Releases qdwf_solve's per-context state (pinned copy, event, graph), or
+// only its cached graph (after anything that changes the launches it holds).
+void forget_solver_state(qdwf_ctx* c);
+void forget_graph(qdwf_ctx* c);
+
+}  // namespace qdwf
+
 struct qdwf_ctx {
   qdwf_action act;
   int device;
   qdwf::Geom g;
+  std::shared_ptr<const qdwf::GeomTables> geo;   // host copy of the site tables
+  void* d_block;           // the context's device block (nullptr when the arrays live
+                           // in memory the context does not own, e.g. a pool arena)
   int32_t* d_nbr;          // [2][8][Vh] neighbour internal index
   int32_t* d_site_lex;     // [2][Vh] lex index of each internal site
   int tile[4];             // tile of the traversal order (1 on the sweep dimension)
   int order[2];            // split and sweep dimension of the traversal order
   void* d_links[4];        // per precision: [2][4][Vh][18] reals, bc folded in
+                           // (nullptr for a precision the context does not keep)
   void* d_dlinks[4];       // per precision (32- and 16-bit, t-sweep geometries only):
                            // [2][Vh][8][18], the 8 links of each site (U_mu(x), then
                            // U_mu(x - mu) taken from the other parity), bc folded in
@@ -130,10 +188,13 @@ struct qdwf_ctx {
   double* d_mat64;         // [MAT_COUNT][2][Ls][Ls]
   float* d_mat32;
   std::vector<double> h_mat;  // host copy
-  std::vector<int32_t> h_nbr; // host copy [2][8][Vh]
-  std::vector<int32_t> h_site_lex;  // [2][Vh]
-  std::vector<int32_t> h_idx;       // [V] internal index of each lex site
-  std::vector<int8_t> h_sign; // [2][8][Vh]
+  // qdwf_solve's reusable host state: pinned copy of the per-rhs CG states
+  // and the round event (created on first use, freed with the context), and
+  // the graph of its inner iterations for the last workspace it was given
+  void* h_pin;
+  size_t h_pin_bytes;
+  hipEvent_t ev;
+  qdwf::SolveGraph graph;
 };
 
 namespace qdwf {

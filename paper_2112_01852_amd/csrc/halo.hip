@@ -218,7 +218,7 @@ int qdwf_split_prepare(qdwf_ctx* ctx, int ranks, int prec, void* ws, void* strea
     return QDWF_OK;
   });
   if (rc == QDWF_OK) {
-    const hipError_t e = hipMemcpyAsync(w + L.idx, ctx->h_idx.data(), sizeof(int32_t) * ctx->g.V,
+    const hipError_t e = hipMemcpyAsync(w + L.idx, ctx->geo->idx.data(), sizeof(int32_t) * ctx->g.V,
                                         hipMemcpyHostToDevice, st);
     if (e == hipSuccess) (void)hipStreamSynchronize(st);
     else rc = fail(QDWF_EDEVICE, "hipMemcpyAsync failed: %s", hipGetErrorString(e));

@@ -1,0 +1,262 @@
+// The Domain Wall kernel's body, shared by the launch over one context
+// (hop.hip) and the grouped launch over many contexts (group.hip): the 4D
+// Wilson hop D_h applied on every slice of the fifth dimension (the kernel
+// Section 4.1 measures; 1320 flops per 5D site in Table 3), fused with the
+// Mobius 5D factors and the 4D-local epilogue so that one pass over memory
+// gives D, D^dag, M_pq, (M_qp)^dag, or the last stage of M_pc / M_pc^dag.
+//
+// Work decomposition (one lane per 5D site and right-hand side):
+//   * a wavefront holds floor(64/Ls) groups of Ls lanes; the lanes of a group
+//     are the Ls slices of one (4D site, rhs) pair, so the s +- 1 neighbours
+//     needed by the 5D operator C live in the same wavefront and are fetched
+//     with cross-lane permutes instead of memory reloads;
+//   * a block covers nsb consecutive checkerboard sites times nrb right-hand
+//     sides; the 8 links of each of its 4D sites (4 forward U_mu(x), 4 backward
+//     U_mu(x-mu)) are staged once in LDS and shared by all Ls*nrb lanes of the
+//     site (Section 4.2 credits the Domain Wall kernel's advantage over Wilson
+//     Dslash to exactly this reuse of links across the fifth dimension);
+//   * the spin projection (1 -+ g_mu) reduces each neighbour spinor to a
+//     half spinor before the SU(3) multiply, so only 2 colour vectors are
+//     multiplied per direction (Table 3 counts this as 1320 flops per site).
+#pragma once
+
+#include "common.h"
+#include "hopcore.h"
+#include "siteio.h"
+#include "spin.h"
+
+namespace qdwf {
+
+struct HopK {
+  const void* in[2];
+  void* out[2];
+  const void* z[2];
+  const void* links;   // [2][4][Vh][18] in the storage type
+  const int* nbr;      // [2][8][Vh]
+  long rs_in, rs_out, rs_z, plane;
+  int Vh, Ls, nrhs, par0, npar;
+  int nsb, nrb, gpw, nrblk;
+  int epi, xcd, minv;
+  double c_over_b, mf, hop_scale_b, alpha, beta;
+  double rpow[4];      // (-beta/alpha)^(2^j), j < 4: the M_ee^-1 scan
+};
+
+// Target occupancy (waves per SIMD) the register allocator plans for: two for
+// 32- and 64-bit storage, whose arithmetic needs the registers to keep two
+// directions' neighbour loads in flight, three for 16-bit storage.
+template <class S> struct WavesPerEU { static constexpr int v = sizeof(S) >= 4 ? 2 : 3; };
+
+// One block's share of a hop launch: logical block L of the launch described
+// by k (its sites, parity and right-hand sides), with smem the block's LDS
+// (the LDS bytes make_hopk reports). Every 5D site's result depends only on k and the site, not
+// on which block or launch computes it.
+template <class S, int LAYOUT, bool DAG, bool DPP16, bool MINV>
+__device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
+  typedef typename Store<S>::compute T;
+  constexpr int LSTR = LinkStride<T>::v;
+  T* su = reinterpret_cast<T*>(smem);                       // [nsb][8][LSTR]
+  int* snb = reinterpret_cast<int*>(su + (size_t)8 * LSTR * k.nsb);   // [8][nsb]
+
+  // logical block L: parity fastest, then sites, then right-hand-side
+  // blocks, so the right-hand sides sweep the lattice one after another and
+  // the working set the caches see is one field at a time
+  const int nsblk = (k.Vh + k.nsb - 1) / k.nsb;
+  const int p = k.par0 + L % k.npar;
+  const int t1 = L / k.npar;
+  const int sb = t1 % nsblk;
+  const int rb = t1 / nsblk;
+  const int q = 1 - p;
+  const int cb0 = sb * k.nsb;
+  const int Vh = k.Vh;
+
+  // Stage the neighbour indices of the block's sites (one load per thread),
+  // then start this lane's first two neighbour-spinor loads, then stage the
+  // links with every load of this thread in flight at once, so the block pays
+  // about two memory latencies before its arithmetic starts.
+  const int* nbp = k.nbr + (long)p * 8 * Vh;
+  for (int i = threadIdx.x; i < 8 * k.nsb; i += blockDim.x) {
+    const int d = i / k.nsb, sl = i - d * k.nsb;
+    const int cb = min(cb0 + sl, Vh - 1);
+    snb[i] = nbp[(long)d * Vh + cb];
+  }
+  __syncthreads();
+
+  const int Ls = DPP16 ? 16 : k.Ls;   // a constant on the Ls = 16 path
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gl = lane / Ls, s = lane - gl * Ls;
+  const bool lane_ok = gl < k.gpw;
+  const int gid = wave * k.gpw + (lane_ok ? gl : 0);
+  const int sl = gid / k.nrb, rl = gid - sl * k.nrb;
+  const int cb = cb0 + sl, r = rb * k.nrb + rl;
+  const bool active = lane_ok && cb < Vh && r < k.nrhs;
+  const int rc = min(r, k.nrhs - 1);
+  const int cbc = min(cb, Vh - 1);
+  const S* in = reinterpret_cast<const S*>(k.in[p]) + (long)rc * k.rs_in;
+  const int* nbs = snb + sl;
+
+  T va[24], vb[24];   // two neighbour spinors in flight
+  SiteIO<S, LAYOUT>::load(in, nbs[0], s, Ls, k.plane, va);
+  SiteIO<S, LAYOUT>::load(in, nbs[k.nsb], s, Ls, k.plane, vb);
+
+  {
+    // one thread per link: 18 contiguous reals, loaded with vector loads
+    const S* lk = reinterpret_cast<const S*>(k.links);
+    const int nlink = 8 * k.nsb;
+    for (int i = threadIdx.x; i < nlink; i += blockDim.x) {
+      const int d = i / k.nsb, sl2 = i - d * k.nsb;
+      const int mu = d & 3;
+      int par, site;
+      if (d < 4) { par = p; site = min(cb0 + sl2, Vh - 1); }
+      else       { par = q; site = snb[d * k.nsb + sl2]; }
+      T Ul[18];
+      LinkIO<S>::load(lk + (((long)par * 4 + mu) * Vh + site) * 18, Ul);
+      T* dstp = su + (sl2 * 8 + d) * LSTR;
+#pragma unroll
+      for (int c = 0; c < 18; ++c) dstp[c] = Ul[c];
+    }
+  }
+  __syncthreads();
+
+  const int base = gl * Ls;
+  SShift<DPP16> sh;
+  sh.src_m = lane_ok ? base + (s == 0 ? Ls - 1 : s - 1) : lane;   // holds slice s-1
+  sh.src_p = lane_ok ? base + (s == Ls - 1 ? 0 : s + 1) : lane;   // holds slice s+1
+  const T mf = (T)k.mf;
+  const T wm = (s == 0) ? -mf : (T)1;        // wall factor of S_d at this slice
+  const T wp = (s == Ls - 1) ? -mf : (T)1;   // wall factor of S_u at this slice
+  // A = b (1 + (c/b) C); the factor b is applied once at the end
+  const T cb_ = (T)k.c_over_b;
+  const T cm = cb_ * wm, cp = cb_ * wp;
+  const T* lks = su + sl * 8 * LSTR;
+
+  T acc[24];
+  // direction D uses the buffer loaded two steps earlier and refills it with
+  // direction D + 2
+  auto step = [&](auto Dc) {
+    constexpr int D = decltype(Dc)::value;
+    constexpr int MU = D & 3;
+    constexpr bool FWD = D < 4;
+    // (1 - g) on forward hops and (1 + g) on backward ones; swapped for D_h^dag
+    constexpr int SG = (FWD != DAG) ? -1 : +1;
+    T* buf = (D & 1) ? vb : va;
+    T v[24];
+#pragma unroll
+    for (int i = 0; i < 24; ++i) v[i] = buf[i];
+    if constexpr (D < 6)
+      SiteIO<S, LAYOUT>::load(in, nbs[(D + 2) * k.nsb], s, Ls, k.plane, buf);
+    if constexpr (!DAG) {
+      // chi / b = psi + (c/b) (P+ psi_{s-1} + P- psi_{s+1}), walls included
+      T w[24];
+#pragma unroll
+      for (int i = 0; i < 24; ++i) w[i] = v[i];
+      shift_s<1, 15>(sh, cm, cp, w, v);
+    }
+    T h[12], uh[12], U[18];
+    load_link(lks + D * LSTR, U);
+    project<MU, SG>(v, h);
+    su3_mul<!FWD>(U, h, uh);
+    recon_acc<MU, SG, D == 0>(uh, acc);
+  };
+  step(IC<0>()); step(IC<1>()); step(IC<2>()); step(IC<3>());
+  step(IC<4>()); step(IC<5>()); step(IC<6>()); step(IC<7>());
+
+  if constexpr (DAG) {
+    // A^dag h / b = h + (c/b) C^dag h, C^dag = P- S_d + P+ S_u:
+    // upper spins come from s+1, lower spins from s-1
+    T tmp[24];
+#pragma unroll
+    for (int i = 0; i < 24; ++i) tmp[i] = acc[i];
+    shift_s<15, 1>(sh, cp, cm, acc, tmp);
+#pragma unroll
+    for (int i = 0; i < 24; ++i) acc[i] = tmp[i];
+  }
+  if constexpr (MINV) {
+    {
+      // out = M_ee^-1 (or M_ee^-dag) applied to the hop result, across the 16
+      // slices of the row: (alpha + beta S)^-1 on each chirality is a cyclic
+      // geometric series in S, summed by doubling (steps 1, 2, 4, 8), with -mf
+      // on the terms that wrap; its common factor is folded into the scale.
+      // M_ee: upper spins see S_d (slice s - d), lower spins S_u (s + d);
+      // the adjoint swaps them.
+      auto scan = [&](auto Jc) {
+        constexpr int J = decltype(Jc)::value;
+        constexpr int Dd = 1 << J;
+        const T rp = (T)k.rpow[J];
+        const T cdn = (s - Dd < 0) ? rp * (-mf) : rp;    // source slice s - d
+        const T cup = (s + Dd >= 16) ? rp * (-mf) : rp;  // source slice s + d
+        T src[24];
+#pragma unroll
+        for (int i = 0; i < 24; ++i) src[i] = acc[i];
+        if constexpr (DAG) shift_s<16 - Dd, Dd>(sh, cup, cdn, src, acc);
+        else shift_s<Dd, 16 - Dd>(sh, cdn, cup, src, acc);
+      };
+      scan(IC<0>()); scan(IC<1>()); scan(IC<2>()); scan(IC<3>());
+    }
+  }
+  const T hs = (T)k.hop_scale_b;   // hop scale times b (and the M_ee^-1 factor)
+  if (k.epi) {
+    const S* zf = reinterpret_cast<const S*>(k.z[p]) + (long)rc * k.rs_z;
+    T z[24];
+    SiteIO<S, LAYOUT>::load(zf, cbc, s, Ls, k.plane, z);
+    const T al = (T)k.alpha, be = (T)k.beta;
+    const T bm = be * wm, bp = be * wp;
+#pragma unroll
+    for (int i = 0; i < 24; ++i) acc[i] = fmac(al, z[i], hs * acc[i]);
+    if constexpr (!DAG) shift_s<1, 15>(sh, bm, bp, z, acc);   // + beta C z
+    else shift_s<15, 1>(sh, bp, bm, z, acc);                  // + beta C^dag z
+  } else {
+#pragma unroll
+    for (int i = 0; i < 24; ++i) acc[i] *= hs;
+  }
+  if (active) {
+    S* out = reinterpret_cast<S*>(k.out[p]) + (long)rc * k.rs_out;
+    SiteIO<S, LAYOUT>::store(out, cbc, s, Ls, k.plane, acc);
+  }
+}
+
+
+// Kernel arguments of a hop launch on one context (HopArgs as for
+// launch_hop, the launch shape sh), its LDS bytes per block and its number of
+// logical blocks. MINV: M_ee^-1 fused (Ls = 16 only).
+template <class S, bool MINV>
+int make_hopk(const qdwf_ctx* ctx, int prec, const HopArgs& a, const HopShape& sh, HopK* k,
+              size_t* lds, int* nblocks) {
+  typedef typename Store<S>::compute T;
+  const Geom& g = ctx->g;
+  for (int i = 0; i < 2; ++i) { k->in[i] = a.in[i]; k->out[i] = a.out[i]; k->z[i] = a.z[i]; }
+  k->links = a.links ? a.links : ctx->d_links[prec];
+  k->nbr = ctx->d_nbr;
+  k->rs_in = a.rs_in; k->rs_out = a.rs_out; k->rs_z = a.rs_z;
+  k->plane = g.n5h;
+  k->Vh = g.Vh; k->Ls = g.Ls; k->nrhs = a.nrhs; k->par0 = a.par0; k->npar = a.npar;
+  k->gpw = 64 / g.Ls;
+  const int G = (sh.threads / 64) * k->gpw;
+  k->nrb = sh.nrb;
+  k->nsb = G / sh.nrb;
+  k->nrblk = (a.nrhs + k->nrb - 1) / k->nrb;
+  const int nsblk = (g.Vh + k->nsb - 1) / k->nsb;
+  k->epi = a.epi; k->xcd = sh.xcd;
+  k->c_over_b = ctx->act.c / ctx->act.b;
+  k->mf = ctx->act.mf;
+  k->hop_scale_b = a.hop_scale * ctx->act.b;
+  k->alpha = a.alpha; k->beta = a.beta;
+  k->minv = MINV;
+  if (MINV) {
+    if (a.epi) return fail(QDWF_EINVAL, "fused M_ee^-1 takes no epilogue term");
+    const double al = ctx->act.b * (4.0 - ctx->act.M5) + 1.0;
+    const double be = ctx->act.c * (4.0 - ctx->act.M5) - 1.0;
+    double r = -be / al;
+    for (int j = 0; j < 4; ++j) { k->rpow[j] = r; r *= r; }
+    // r is now (-beta/alpha)^16 = (-beta/alpha)^Ls
+    k->hop_scale_b /= al * (1.0 + ctx->act.mf * r);
+  } else {
+    for (int j = 0; j < 4; ++j) k->rpow[j] = 0.0;
+  }
+  *lds = (size_t)8 * LinkStride<T>::v * k->nsb * sizeof(T) + (size_t)8 * k->nsb * sizeof(int) +
+                    (size_t)sh.lds_pad;
+  if (*lds > 64 * 1024) return fail(QDWF_EINVAL, "hop launch shape needs %zu bytes of LDS", *lds);
+  *nblocks = nsblk * k->nrblk * a.npar;
+  return QDWF_OK;
+}
+
+}  // namespace qdwf

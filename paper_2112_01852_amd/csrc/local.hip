@@ -11,8 +11,7 @@
 // each lane forms its output slice as an Ls-term sum over the staged column.
 #include <cmath>
 
-#include "common.h"
-#include "siteio.h"
+#include "localbody.h"
 
 namespace qdwf {
 
@@ -24,46 +23,10 @@ __global__ void __launch_bounds__(256) local_kernel(const S* in, S* out,
                                                     const typename Store<S>::compute* __restrict__ K,
                                                     int Vh, int Ls, long plane, long rs_half,
                                                     long rs, int nhalf) {
-  typedef typename Store<S>::compute T;
   extern __shared__ __align__(16) unsigned char smem[];
-  T* col = reinterpret_cast<T*>(smem);           // [groups][Ls][24]
-  T* km = col + (blockDim.x / 64) * (64 / Ls) * Ls * 24;   // [2][Ls][Ls]
-  for (int i = threadIdx.x; i < 2 * Ls * Ls; i += blockDim.x) km[i] = K[i];
-
-  const int gpw = 64 / Ls;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int gl = lane / Ls, s = lane - gl * Ls;
-  const bool lane_ok = gl < gpw;
-  const int gid = wave * gpw + (lane_ok ? gl : 0);
-  const int G = (blockDim.x / 64) * gpw;
-  const int cb = blockIdx.x * G + gid;
-  const bool active = lane_ok && cb < Vh;
-  const int cbc = min(cb, Vh - 1);
   const int h = blockIdx.y % nhalf, r = blockIdx.y / nhalf;
   const long off = (long)r * rs + (long)h * rs_half;
-
-  T v[24];
-  SiteIO<S, LAYOUT>::load(in + off, cbc, s, Ls, plane, v);
-  if (lane_ok) {
-#pragma unroll
-    for (int c = 0; c < 24; ++c) col[(gid * Ls + s) * 24 + c] = v[c];
-  }
-  __syncthreads();
-  if (!active) return;
-  T o[24];
-#pragma unroll
-  for (int c = 0; c < 24; ++c) o[c] = 0;
-  const T* ku = km + s * Ls;              // upper chirality row s
-  const T* kl = km + Ls * Ls + s * Ls;    // lower chirality row s
-  const T* cg = col + gid * Ls * 24;
-  for (int t = 0; t < Ls; ++t) {
-    const T a = ku[t], b = kl[t];
-#pragma unroll
-    for (int c = 0; c < 12; ++c) o[c] += a * cg[t * 24 + c];
-#pragma unroll
-    for (int c = 12; c < 24; ++c) o[c] += b * cg[t * 24 + c];
-  }
-  SiteIO<S, LAYOUT>::store(out + off, cbc, s, Ls, plane, o);
+  local_block<S, LAYOUT>(in + off, out + off, K, Vh, Ls, plane, blockIdx.x, smem);
 }
 
 }  // namespace

@@ -138,6 +138,7 @@ int launch_pack_links(qdwf_ctx* ctx, const void* U, int canon_prec, hipStream_t 
   auto go = [&](auto rtag, auto stag, void* out) -> int {
     typedef decltype(rtag) R;
     typedef decltype(stag) S;
+    if (!out) return QDWF_OK;   // a precision this context does not keep
     hipLaunchKernelGGL((link_kernel<R, S>), dim3(grid_for(total)), dim3(256), 0, st, U,
                        reinterpret_cast<S*>(out), g.Vh, g.V, ctx->d_site_lex, g.L[0], g.L[1],
                        g.L[2], g.L[3],

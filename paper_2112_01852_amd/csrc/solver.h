@@ -5,7 +5,7 @@
 
 namespace qdwf {
 
-enum { ST_RUN = 0, ST_UPDATE = 1, ST_DONE = 2, ST_NAN = 3, ST_BREAKDOWN = 4 };
+enum { ST_RUN = 0, ST_UPDATE = 1, ST_DONE = 2, ST_NAN = 3, ST_BREAKDOWN = 4, ST_NOTCONV = 5 };
 
 // Per right-hand-side CG state, resident on the device.
 struct RhsState {
@@ -21,7 +21,24 @@ struct RhsState {
   double rr_true;      // last FP64 true |b - A x|^2
   int status, iters, ru;
   int fresh;           // set by a reliable update, cleared by the next iteration
+  int first;           // the next reliable update is the initial one
+  int final;           // out of iterations: the next reliable update ends the solve
+  int max_iter;        // iteration limit kept on the device (0: the host enforces it)
 };
+
+inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Workspace of a solve of nrhs right-hand sides of n reals: byte offsets of
+// its vectors, each on a 256-byte boundary.
+struct Layout {
+  // FP64 vectors: r_hi, Ax, v_hi, te1_hi, te2_hi
+  size_t off_rh, off_ax, off_vh, off_t1h, off_t2h;
+  // inner: x_lo, r_lo (R type); p, Ap, v, te1, te2 (S type)
+  size_t off_xl, off_rl, off_p, off_ap, off_v, off_t1, off_t2;
+  size_t off_part, off_state, off_stage;
+  size_t total;
+};
+Layout solver_layout(long n, int nrhs, int inner);
 
 int reduce_blocks(long n);
 int apply_hop_parity(qdwf_ctx* ctx, int prec, int layout, int dagger, int out_par, void* out,
@@ -37,23 +54,5 @@ size_t dot_ws_bytes(long n, int nrhs);
 size_t solve_ws_bytes(const qdwf_ctx* ctx, int inner, int nrhs, int system);
 int solve(qdwf_ctx* ctx, double* x, const double* b, int nrhs, const qdwf_solve_params& prm,
           qdwf_solve_stats* stats, void* ws, hipStream_t st);
-
-// Resumable normal-equation CG on odd half fields (stride = one half field):
-// begin() launches the set-up, then complete() waits for the last round and
-// launch() starts the next one, until complete() reports finished.
-struct Solver {
-  virtual ~Solver() {}
-  virtual int begin() = 0;
-  virtual int launch() = 0;
-  virtual int complete(bool* finished) = 0;
-  virtual void fill_stats(qdwf_solve_stats* stats) const = 0;
-  virtual int result() const = 0;
-};
-Solver* make_solver(qdwf_ctx* ctx, const qdwf_solve_params& prm, int nrhs, double* x,
-                    const double* b, void* ws, hipStream_t st);
-
-// Geometry-only sizes used for admission control.
-size_t ctx_bytes(const qdwf_action& a);
-size_t solve_ws_bytes_for(const qdwf_action& a, int inner, int nrhs);
 
 }  // namespace qdwf

@@ -23,110 +23,89 @@
 #include <cmath>
 #include <initializer_list>
 
-#include "common.h"
-#include "solver.h"
+#include "cgbody.h"
 
 namespace qdwf {
 
 namespace {
 
-constexpr int RT = 256;   // threads of reduction / BLAS kernels
-
-__device__ inline double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-  for (int w = RT / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
-  return r;
-}
-
-template <class S> __device__ inline double rd(const S* p, long i) {
-  return (double)Store<S>::to(p[i]);
-}
-
-// Work split of the vectorised BLAS kernels: block b takes a contiguous range
-// of tiles of 512 reals (one stream per block through memory), its wavefronts
-// taking the tiles in turn, and in tile t lane l owns the reals
-// t*512 + j*64*E + l*E + e (j < 8/E, e < E), E = 16 bytes over the widest
-// storage type of the kernel's fields. Every load or store of E reals is then
-// one piece of a contiguous run across the wavefront.
-constexpr int TILE = 512;
-
-template <int BYTES> struct Word;
-template <> struct Word<16> { typedef uint4 t; };
-template <> struct Word<8> { typedef uint2 t; };
-template <> struct Word<4> { typedef uint32_t t; };
-
-// E consecutive reals of storage type S <-> compute values (one aligned word).
-template <class S, int E> struct Chunk {
-  typedef typename Word<E * (int)sizeof(S)>::t W;
-  template <class T> __device__ static inline void ld(const S* __restrict__ p, T* v) {
-    const W w = *reinterpret_cast<const W*>(p);
-    S e[E];
-    __builtin_memcpy(e, &w, sizeof(e));
-#pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = (T)Store<S>::to(e[k]);
-  }
-  template <class T> __device__ static inline void st(S* __restrict__ p, const T* v) {
-    S e[E];
-#pragma unroll
-    for (int k = 0; k < E; ++k) e[k] = Store<S>::from((typename Store<S>::compute)v[k]);
-    W w;
-    __builtin_memcpy(&w, e, sizeof(e));
-    *reinterpret_cast<W*>(p) = w;
-  }
-};
-
-template <class A, class B, class C = A>
-struct ChunkWidth {
-  static constexpr int maxb = sizeof(A) > sizeof(B) ? (sizeof(A) > sizeof(C) ? sizeof(A) : sizeof(C))
-                                                     : (sizeof(B) > sizeof(C) ? sizeof(B) : sizeof(C));
-  static constexpr int e = 16 / maxb;
-};
-
-// Whether arrays of storage type S at these addresses, with right-hand-side
-// stride rs reals, can be walked in 16-byte words.
-template <class S> inline bool vec_ok(long rs, std::initializer_list<const void*> ptrs) {
-  if (((rs * (long)sizeof(S)) & 15) != 0) return false;
-  for (const void* q : ptrs)
-    if (reinterpret_cast<uintptr_t>(q) & 15) return false;
-  return true;
-}
-
-// part[r*NB + blk] = sum over this block's share of a_r . b_r (all reals);
-// vec: both fields can be read in aligned words (see TILE).
+// Launches over one context's right-hand sides: grid x = blocks of a field,
+// y = right-hand side (per-right-hand-side steps: x = right-hand side).
 template <class SA, class SB>
 __global__ void __launch_bounds__(RT) k_dot(const SA* __restrict__ a, const SB* __restrict__ b,
                                             long n, long rsa, long rsb, double* __restrict__ part,
                                             int vec) {
   __shared__ double sh[RT];
-  const int r = blockIdx.y, NB = gridDim.x;
-  const SA* ar = a + (long)r * rsa;
-  const SB* br = b + (long)r * rsb;
-  double acc = 0;
-  constexpr int E = ChunkWidth<SA, SB>::e;
-  const long nt = vec ? n / TILE : 0;
-  const int lane = threadIdx.x & 63;
-  const long t1 = nt * (blockIdx.x + 1) / NB;   // this block's contiguous range of tiles
-  for (long t = nt * blockIdx.x / NB + (threadIdx.x >> 6); t < t1; t += RT / 64) {
-#pragma unroll
-    for (int j = 0; j < 8 / E; ++j) {
-      const long i = t * TILE + j * 64 * E + lane * E;
-      double x[E], y[E];
-      Chunk<SA, E>::ld(ar + i, x);
-      Chunk<SB, E>::ld(br + i, y);
-#pragma unroll
-      for (int k = 0; k < E; ++k) acc += x[k] * y[k];
-    }
-  }
-  for (long i = TILE * nt + (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)NB * RT)
-    acc += rd(ar, i) * rd(br, i);
-  const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[(long)r * NB + blockIdx.x] = t;
+  k_dot_body<SA, SB>(a, b, n, rsa, rsb, part, vec, blockIdx.x, gridDim.x, blockIdx.y, sh);
+}
+
+__global__ void __launch_bounds__(RT) k_alpha(const double* __restrict__ part, int NB,
+                                              RhsState* __restrict__ st) {
+  __shared__ double sh[RT];
+  k_alpha_body(part, NB, st, blockIdx.x, sh);
+}
+
+template <class SX, class SR, class SP>
+__global__ void __launch_bounds__(RT) k_update_xr(SX* __restrict__ x, SR* __restrict__ r,
+                                                  const SP* __restrict__ p,
+                                                  const SP* __restrict__ Ap, long n, long rs,
+                                                  const RhsState* __restrict__ st,
+                                                  double* __restrict__ part, int vec) {
+  __shared__ double sh[RT];
+  k_update_xr_body<SX, SR, SP>(x, r, p, Ap, n, rs, st, part, vec, blockIdx.x, gridDim.x,
+                               blockIdx.y, sh);
+}
+
+__global__ void __launch_bounds__(RT) k_beta(const double* __restrict__ part, int NB,
+                                             RhsState* __restrict__ st, double delta2) {
+  __shared__ double sh[RT];
+  k_beta_body(part, NB, st, delta2, blockIdx.x, sh);
+}
+
+template <class SR, class SP>
+__global__ void __launch_bounds__(RT) k_update_p(const SR* __restrict__ r, SP* __restrict__ p,
+                                                 long n, long rs, const RhsState* __restrict__ st,
+                                                 int vec) {
+  k_update_p_body<SR, SP>(r, p, n, rs, st, vec, blockIdx.x, gridDim.x, blockIdx.y, nullptr);
+}
+
+template <class SX>
+__global__ void __launch_bounds__(RT) k_fold_x(double* __restrict__ xh, SX* __restrict__ xl,
+                                               long n, long rs_h, long rs,
+                                               const RhsState* __restrict__ st) {
+  k_fold_x_body<SX>(xh, xl, n, rs_h, rs, st, blockIdx.x, gridDim.x, blockIdx.y, nullptr);
+}
+
+__global__ void __launch_bounds__(RT) k_resid(const double* __restrict__ b,
+                                              const double* __restrict__ Ax,
+                                              double* __restrict__ rh, long n, long rs_b,
+                                              long rs, double* __restrict__ part) {
+  __shared__ double sh[RT];
+  k_resid_body(b, Ax, rh, n, rs_b, rs, part, blockIdx.x, gridDim.x, blockIdx.y, sh);
+}
+
+__global__ void __launch_bounds__(RT) k_ru_decide(const double* __restrict__ part, int NB,
+                                                  RhsState* __restrict__ st, double tol2,
+                                                  double nreal, int scale, int first) {
+  __shared__ double sh[RT];
+  k_ru_decide_body(part, NB, st, tol2, nreal, scale, first, blockIdx.x, sh);
+}
+
+template <class SR, class SP>
+__global__ void __launch_bounds__(RT) k_ru_apply(const double* __restrict__ rh,
+                                                 SR* __restrict__ rl, SP* __restrict__ p, long n,
+                                                 long rs, const RhsState* __restrict__ st) {
+  k_ru_apply_body<SR, SP>(rh, rl, p, n, rs, st, blockIdx.x, gridDim.x, blockIdx.y, nullptr);
+}
+
+__global__ void k_init_state(RhsState* st, const double* part, int NB) {
+  __shared__ double sh[RT];
+  k_init_state_body(st, part, NB, 0, blockIdx.x, sh);
+}
+
+template <class S>
+__global__ void k_zero(S* __restrict__ x, long n, long rs) {
+  k_zero_body<S>(x, n, rs, blockIdx.x, gridDim.x, blockIdx.y, nullptr);
 }
 
 // Imaginary part of <a, b> = sum a_re b_im - a_im b_re, per layout.
@@ -167,264 +146,9 @@ __global__ void __launch_bounds__(RT) k_sum(const double* __restrict__ part, int
   if (threadIdx.x == 0) out[(long)r * stride] = t;
 }
 
-__device__ inline double part_sum(const double* part, int NB, double* sh) {
-  const int r = blockIdx.x;
-  double acc = 0;
-  for (int i = threadIdx.x; i < NB; i += RT) acc += part[(long)r * NB + i];
-  return block_sum(acc, sh);
-}
-
-// alpha = rr / <p, Ap>
-__global__ void __launch_bounds__(RT) k_alpha(const double* __restrict__ part, int NB,
-                                              RhsState* __restrict__ st) {
-  __shared__ double sh[RT];
-  const double pAp = part_sum(part, NB, sh);
-  if (threadIdx.x) return;
-  RhsState& s = st[blockIdx.x];
-  s.fresh = 0;
-  if (s.status != ST_RUN) return;
-  s.pAp = pAp;
-  if (!(pAp > 0.0) || !isfinite(pAp)) {
-    s.status = ST_BREAKDOWN;
-    s.alpha = 0.0;
-    return;
-  }
-  s.alpha = s.rr / pAp;
-}
-
-// x += alpha p ; r -= alpha Ap ; partial |r|^2
-template <class SX, class SR, class SP>
-__global__ void __launch_bounds__(RT) k_update_xr(SX* __restrict__ x, SR* __restrict__ r,
-                                                  const SP* __restrict__ p,
-                                                  const SP* __restrict__ Ap, long n, long rs,
-                                                  const RhsState* __restrict__ st,
-                                                  double* __restrict__ part, int vec) {
-  __shared__ double sh[RT];
-  typedef typename Store<SR>::compute T;
-  const int q = blockIdx.y, NB = gridDim.x;
-  const RhsState& s = st[q];
-  if (s.status != ST_RUN) {
-    if (threadIdx.x == 0) part[(long)q * NB + blockIdx.x] = 0.0;
-    return;
-  }
-  const T al = (T)s.alpha;
-  SX* xr = x + (long)q * rs;
-  SR* rr = r + (long)q * rs;
-  const SP* pr = p + (long)q * rs;
-  const SP* ar = Ap + (long)q * rs;
-  double acc = 0;
-  constexpr int E = ChunkWidth<SX, SR, SP>::e;
-  const long nt = vec ? n / TILE : 0;
-  const int lane = threadIdx.x & 63;
-  const long t1 = nt * (blockIdx.x + 1) / NB;   // this block's contiguous range of tiles
-  for (long t = nt * blockIdx.x / NB + (threadIdx.x >> 6); t < t1; t += RT / 64) {
-#pragma unroll
-    for (int j = 0; j < 8 / E; ++j) {
-      const long i = t * TILE + j * 64 * E + lane * E;
-      T pv[E], av[E], xv[E], rv[E];
-      Chunk<SP, E>::ld(pr + i, pv);
-      Chunk<SP, E>::ld(ar + i, av);
-      Chunk<SX, E>::ld(xr + i, xv);
-      Chunk<SR, E>::ld(rr + i, rv);
-#pragma unroll
-      for (int k = 0; k < E; ++k) {
-        xv[k] = xv[k] + al * pv[k];
-        rv[k] = rv[k] - al * av[k];
-      }
-      Chunk<SX, E>::st(xr + i, xv);
-      Chunk<SR, E>::st(rr + i, rv);
-#pragma unroll
-      for (int k = 0; k < E; ++k) acc += (double)rv[k] * (double)rv[k];
-    }
-  }
-  for (long i = TILE * nt + (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)NB * RT) {
-    const T pv = (T)Store<SP>::to(pr[i]);
-    const T av = (T)Store<SP>::to(ar[i]);
-    xr[i] = Store<SX>::from((T)Store<SX>::to(xr[i]) + al * pv);
-    const T rv = (T)Store<SR>::to(rr[i]) - al * av;
-    rr[i] = Store<SR>::from(rv);
-    acc += (double)rv * (double)rv;
-  }
-  const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[(long)q * NB + blockIdx.x] = t;
-}
-
-// beta = rr_new / rr ; decide whether a reliable update is due
-__global__ void __launch_bounds__(RT) k_beta(const double* __restrict__ part, int NB,
-                                             RhsState* __restrict__ st, double delta2) {
-  __shared__ double sh[RT];
-  const double rr_new = part_sum(part, NB, sh);
-  if (threadIdx.x) return;
-  RhsState& s = st[blockIdx.x];
-  if (s.status != ST_RUN) return;
-  s.iters += 1;
-  if (!isfinite(rr_new)) {
-    s.status = ST_NAN;
-    return;
-  }
-  s.rr_prev = s.rr;
-  s.rr = rr_new;
-  s.beta = rr_new / s.rr_prev;
-  if (rr_new <= s.thresh || rr_new < delta2 * s.rr_ru) s.status = ST_UPDATE;
-}
-
-// p = r + beta p
-template <class SR, class SP>
-__global__ void __launch_bounds__(RT) k_update_p(const SR* __restrict__ r, SP* __restrict__ p,
-                                                 long n, long rs, const RhsState* __restrict__ st,
-                                                 int vec) {
-  typedef typename Store<SR>::compute T;
-  const int q = blockIdx.y, NB = gridDim.x;
-  const RhsState& s = st[q];
-  if (s.status != ST_RUN) return;
-  const T be = (T)s.beta;
-  const SR* rr = r + (long)q * rs;
-  SP* pr = p + (long)q * rs;
-  constexpr int E = ChunkWidth<SR, SP>::e;
-  const long nt = vec ? n / TILE : 0;
-  const int lane = threadIdx.x & 63;
-  const long t1 = nt * (blockIdx.x + 1) / NB;   // this block's contiguous range of tiles
-  for (long t = nt * blockIdx.x / NB + (threadIdx.x >> 6); t < t1; t += RT / 64) {
-#pragma unroll
-    for (int j = 0; j < 8 / E; ++j) {
-      const long i = t * TILE + j * 64 * E + lane * E;
-      T rv[E], pv[E];
-      Chunk<SR, E>::ld(rr + i, rv);
-      Chunk<SP, E>::ld(pr + i, pv);
-#pragma unroll
-      for (int k = 0; k < E; ++k) pv[k] = rv[k] + be * pv[k];
-      Chunk<SP, E>::st(pr + i, pv);
-    }
-  }
-  for (long i = TILE * nt + (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)NB * RT)
-    pr[i] = Store<SP>::from((T)Store<SR>::to(rr[i]) + be * (T)Store<SP>::to(pr[i]));
-}
-
-// ---- reliable update -------------------------------------------------------
-// x_hi += x_lo / sigma ; x_lo = 0   (rhs that are running or waiting)
-template <class SX>
-__global__ void __launch_bounds__(RT) k_fold_x(double* __restrict__ xh, SX* __restrict__ xl,
-                                               long n, long rs_h, long rs,
-                                               const RhsState* __restrict__ st) {
-  const int q = blockIdx.y, NB = gridDim.x;
-  const RhsState& s = st[q];
-  if (s.status != ST_UPDATE) return;
-  const double inv = 1.0 / s.sigma;
-  double* xr = xh + (long)q * rs_h;
-  SX* lr = xl + (long)q * rs;
-  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)NB * RT) {
-    xr[i] += (double)Store<SX>::to(lr[i]) * inv;
-    lr[i] = Store<SX>::from(0);
-  }
-}
-
-// r_hi = b - Ax ; partial |r_hi|^2 (also for finished rhs, for reporting)
-__global__ void __launch_bounds__(RT) k_resid(const double* __restrict__ b,
-                                              const double* __restrict__ Ax,
-                                              double* __restrict__ rh, long n, long rs_b,
-                                              long rs, double* __restrict__ part) {
-  __shared__ double sh[RT];
-  const int q = blockIdx.y, NB = gridDim.x;
-  const double* br = b + (long)q * rs_b;
-  const double* ar = Ax + (long)q * rs;
-  double* rr = rh + (long)q * rs;
-  double acc = 0;
-  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)NB * RT) {
-    const double v = br[i] - ar[i];
-    rr[i] = v;
-    acc += v * v;
-  }
-  const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[(long)q * NB + blockIdx.x] = t;
-}
-
-// decide after the true residual: converged, or restart the inner recursion
-__global__ void __launch_bounds__(RT) k_ru_decide(const double* __restrict__ part, int NB,
-                                                  RhsState* __restrict__ st, double tol2,
-                                                  double nreal, int scale, int first) {
-  __shared__ double sh[RT];
-  const double rr_true = part_sum(part, NB, sh);
-  if (threadIdx.x) return;
-  RhsState& s = st[blockIdx.x];
-  // only right-hand sides that asked for an update take it, so a batched
-  // solve follows exactly the trajectory each right-hand side has alone
-  if (s.status != ST_UPDATE) return;
-  s.rr_true = rr_true;
-  if (first) {
-    // initial residual: p starts as r
-    s.w_r = 1.0;
-    s.beta = 0.0;
-  } else {
-    // the paused step still owes its p update: beta from the true residual
-    s.ru += 1;
-    const double rr_prev_phys = s.rr_prev / (s.sigma * s.sigma);
-    s.w_r = 1.0;
-    s.beta = rr_true / rr_prev_phys;
-  }
-  s.fresh = 1;
-  if (!isfinite(rr_true)) {
-    s.status = ST_NAN;
-    return;
-  }
-  if (rr_true <= tol2 * s.bb) {
-    s.status = ST_DONE;
-    return;
-  }
-  const double sig = scale ? sqrt(nreal / rr_true) : 1.0;
-  s.sigma_ratio = first ? 0.0 : sig / s.sigma;
-  s.sigma = sig;
-  s.rr = sig * sig * rr_true;
-  s.rr_ru = s.rr;
-  s.thresh = tol2 * s.bb * sig * sig;
-  s.status = ST_RUN;
-}
-
-// r_lo = sigma r_hi ; p = w_r sigma r_hi + beta sigma_ratio p
-template <class SR, class SP>
-__global__ void __launch_bounds__(RT) k_ru_apply(const double* __restrict__ rh,
-                                                 SR* __restrict__ rl, SP* __restrict__ p, long n,
-                                                 long rs, const RhsState* __restrict__ st) {
-  const int q = blockIdx.y, NB = gridDim.x;
-  const RhsState& s = st[q];
-  if (s.status != ST_RUN || !s.fresh) return;
-  typedef typename Store<SR>::compute T;
-  const double sg = s.sigma, wr = s.w_r, bs = s.beta * s.sigma_ratio;
-  const double* hr = rh + (long)q * rs;
-  SR* lr = rl + (long)q * rs;
-  SP* pr = p + (long)q * rs;
-  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)NB * RT) {
-    const double v = sg * hr[i];
-    lr[i] = Store<SR>::from((T)v);
-    const double pv = (bs != 0.0) ? bs * (double)Store<SP>::to(pr[i]) : 0.0;
-    pr[i] = Store<SP>::from((typename Store<SP>::compute)(wr * v + pv));
-  }
-}
-
 __global__ void k_force_update(RhsState* st, int nrhs) {
   for (int q = threadIdx.x; q < nrhs; q += blockDim.x)
     if (st[q].status == ST_RUN) st[q].status = ST_UPDATE;
-}
-
-__global__ void k_init_state(RhsState* st, const double* part, int NB, int nrhs) {
-  // bb from the partials of |b|^2
-  __shared__ double sh[RT];
-  const double bb = part_sum(part, NB, sh);
-  if (threadIdx.x) return;
-  RhsState& s = st[blockIdx.x];
-  RhsState z = {};
-  s = z;
-  s.bb = bb;
-  s.sigma = 1.0;
-  s.status = !isfinite(bb) ? ST_NAN : (bb > 0.0 ? ST_UPDATE : ST_DONE);
-  (void)nrhs;
-}
-
-template <class S>
-__global__ void k_zero(S* __restrict__ x, long n, long rs) {
-  const int q = blockIdx.y, NB = gridDim.x;
-  S* xr = x + (long)q * rs;
-  for (long i = (long)blockIdx.x * RT + threadIdx.x; i < n; i += (long)NB * RT)
-    xr[i] = Store<S>::from(0);
 }
 
 template <class S>
@@ -535,23 +259,25 @@ int dot_re_im(qdwf_ctx* ctx, double* out_host, const void* x, const void* y, lon
   return fail(QDWF_EINVAL, "unknown precision %d", prec);
 }
 
+void forget_graph(qdwf_ctx* c) {
+  if (c->graph.exec) (void)hipGraphExecDestroy(c->graph.exec);
+  c->graph = SolveGraph();
+}
+
+void forget_solver_state(qdwf_ctx* c) {
+  forget_graph(c);
+  if (c->ev) (void)hipEventDestroy(c->ev);
+  c->ev = nullptr;
+  if (c->h_pin) (void)hipHostFree(c->h_pin);
+  c->h_pin = nullptr;
+  c->h_pin_bytes = 0;
+}
+
 size_t dot_ws_bytes(long n, int nrhs) {
   return sizeof(double) * ((size_t)reduce_blocks(n) * nrhs + 2 * (size_t)nrhs) + 256;
 }
 
 // ---- the solver ----------------------------------------------------------------
-namespace {
-
-inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
-
-struct Layout {
-  // FP64 vectors: r_hi, Ax, v_hi, te1_hi, te2_hi
-  size_t off_rh, off_ax, off_vh, off_t1h, off_t2h;
-  // inner: x_lo, r_lo (R type); p, Ap, v, te1, te2 (S type)
-  size_t off_xl, off_rl, off_p, off_ap, off_v, off_t1, off_t2;
-  size_t off_part, off_state, off_stage;
-  size_t total;
-};
 
 Layout solver_layout(long n, int nrhs, int inner) {
   Layout L;
@@ -581,8 +307,10 @@ Layout solver_layout(long n, int nrhs, int inner) {
   return L;
 }
 
+namespace {
+
 template <class S, class R>
-struct Cg : Solver {
+struct Cg {
   qdwf_ctx* ctx;
   hipStream_t st;
   int layout, inner, nrhs;
@@ -648,18 +376,12 @@ struct Cg : Solver {
 
   // ---- resumable driver: begin(), then alternately complete() and launch()
   qdwf_solve_params prm;
-  RhsState* h_pin = nullptr;     // pinned host copy of the device states
-  hipEvent_t ev = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph = nullptr;
+  RhsState* h_pin = nullptr;     // pinned host copy of the device states (the context's)
+  hipEvent_t ev = nullptr;       // the context's round event
   int status = QDWF_OK;
   bool final_round = false;
 
-  ~Cg() override {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (ev) (void)hipEventDestroy(ev);
-    if (h_pin) (void)hipHostFree(h_pin);
+  ~Cg() {
   }
 
   int fetch_async() {
@@ -668,15 +390,26 @@ struct Cg : Solver {
     return QDWF_OK;
   }
 
-  int begin() override {
+  int begin() {
     int rc;
     d_state = at<RhsState>(L.off_state);
     hop_applications = 0;
-    QDWF_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_pin), sizeof(RhsState) * nrhs));
-    QDWF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    // the pinned state copy and the event belong to the context and are
+    // reused by its later solves (the copy grows only for more rhs)
+    const size_t need = sizeof(RhsState) * nrhs;
+    if (ctx->h_pin_bytes < need) {
+      if (ctx->h_pin) (void)hipHostFree(ctx->h_pin);
+      ctx->h_pin = nullptr;
+      ctx->h_pin_bytes = 0;
+      QDWF_HIP(hipHostMalloc(&ctx->h_pin, need));
+      ctx->h_pin_bytes = need;
+    }
+    if (!ctx->ev) QDWF_HIP(hipEventCreateWithFlags(&ctx->ev, hipEventDisableTiming));
+    h_pin = reinterpret_cast<RhsState*>(ctx->h_pin);
+    ev = ctx->ev;
     hipLaunchKernelGGL((k_dot<double, double>), grid(), dim3(RT), 0, st, b, b, n, rs_b, rs_b, part(),
                        vec_ok<double>(rs_b, {b}) ? 1 : 0);
-    hipLaunchKernelGGL(k_init_state, dim3(nrhs), dim3(RT), 0, st, d_state, part(), NB, nrhs);
+    hipLaunchKernelGGL(k_init_state, dim3(nrhs), dim3(RT), 0, st, d_state, part(), NB);
     hipLaunchKernelGGL((k_zero<R>), grid(), dim3(RT), 0, st, at<R>(L.off_xl), n, n);
     if (!prm.x0_is_guess) hipLaunchKernelGGL((k_zero<double>), grid(), dim3(RT), 0, st, xh, n, rs_x);
     QDWF_HIP(hipGetLastError());
@@ -686,7 +419,7 @@ struct Cg : Solver {
 
   // Waits for the last launched round and decides; *finished is set once the
   // solve is over (status holds the outcome).
-  int complete(bool* finished) override {
+  int complete(bool* finished) {
     QDWF_HIP(hipEventSynchronize(ev));
     h_state.assign(h_pin, h_pin + nrhs);
     bool any_run = false, any_upd = false, bad = false;
@@ -708,7 +441,7 @@ struct Cg : Solver {
 
   // Launches the next round (asynchronously): a reliable update if one is
   // due, otherwise `check_every` inner iterations; ends with a state fetch.
-  int launch() override {
+  int launch() {
     int rc = 0;
     bool any_upd = false;
     int max_it = 0;
@@ -732,17 +465,38 @@ struct Cg : Solver {
     }
     const int batch = std::min(k, max_iter - max_it);
     if (prm.use_graph && batch == k) {
-      if (!gexec) {
+      // the k iterations touch only the workspace, so one captured graph
+      // serves every later solve of this context with the same workspace,
+      // right-hand-side count, precisions, k and delta
+      SolveGraph& G = ctx->graph;
+      if (!(G.exec && G.ws == ws && G.nrhs == nrhs && G.inner == inner && G.layout == layout &&
+            G.k == k && G.delta2 == delta2)) {
+        forget_graph(ctx);
         QDWF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         const int64_t h0 = hop_applications;
         for (int i = 0; i < k && !rc; ++i) rc = inner_iteration();
         hop_applications = h0;
+        hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(st, &graph);
-        if (rc) return rc;
+        if (rc) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return rc;
+        }
         if (e != hipSuccess) return fail(QDWF_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
-        QDWF_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e2 != hipSuccess)
+          return fail(QDWF_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(e2));
+        G.exec = exec;
+        G.ws = ws;
+        G.nrhs = nrhs;
+        G.inner = inner;
+        G.layout = layout;
+        G.k = k;
+        G.delta2 = delta2;
       }
-      QDWF_HIP(hipGraphLaunch(gexec, st));
+      QDWF_HIP(hipGraphLaunch(G.exec, st));
       hop_applications += 4 * k;
     } else {
       rc = 0;
@@ -752,9 +506,9 @@ struct Cg : Solver {
     return fetch_async();
   }
 
-  int result() const override { return status; }
+  int result() const { return status; }
 
-  void fill_stats(qdwf_solve_stats* stats) const override {
+  void fill_stats(qdwf_solve_stats* stats) const {
     if (!stats) return;
     stats->iterations = 0;
     stats->reliable_updates = 0;
@@ -804,46 +558,6 @@ int axpby64(double* out, const double* a, double ca, const double* b, double cb,
                      rs_o, rs_a, rs_b);
   QDWF_HIP(hipGetLastError());
   return QDWF_OK;
-}
-
-size_t solve_ws_bytes_for(const qdwf_action& a, int inner, int nrhs) {
-  const long n = (long)a.L[0] * a.L[1] * a.L[2] * a.L[3] / 2 * a.Ls * 24;
-  return solver_layout(n, nrhs, inner).total;
-}
-
-Solver* make_solver(qdwf_ctx* ctx, const qdwf_solve_params& prm, int nrhs, double* x,
-                    const double* b, void* ws, hipStream_t st) {
-  const long n = ctx->g.n5h * 24;
-  auto mk = [&](auto stag, auto rtag) -> Solver* {
-    typedef decltype(stag) S;
-    typedef decltype(rtag) R;
-    Cg<S, R>* cg = new Cg<S, R>();
-    cg->ctx = ctx;
-    cg->st = st;
-    cg->layout = prm.layout;
-    cg->inner = prm.inner_prec;
-    cg->nrhs = nrhs;
-    cg->n = n;
-    cg->NB = reduce_blocks(n);
-    cg->ws = reinterpret_cast<char*>(ws);
-    cg->L = solver_layout(n, nrhs, prm.inner_prec);
-    cg->xh = x;
-    cg->rs_x = n;
-    cg->b = b;
-    cg->rs_b = n;
-    const double delta = prm.delta > 0 ? prm.delta : 0.1;
-    cg->delta2 = prm.inner_prec == QDWF_F64 ? 0.0 : delta * delta;
-    cg->tol2 = prm.tol * prm.tol;
-    cg->prm = prm;
-    return cg;
-  };
-  switch (prm.inner_prec) {
-    case QDWF_F64: return mk(double(), double());
-    case QDWF_F32: return mk(float(), float());
-    case QDWF_F16: return mk(_Float16(), float());
-    case QDWF_BF16: return mk(bf16(), float());
-  }
-  return nullptr;
 }
 
 size_t solve_ws_bytes(const qdwf_ctx* ctx, int inner, int nrhs, int system) {

@@ -212,6 +212,7 @@ int qdwf_tune(qdwf_ctx* ctx, int prec, int layout, int nrhs, void* ws, void* str
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  forget_graph(ctx);   // a solve's cached iterations used the previous shapes
   set_error("");
   if (prev >= 0) (void)hipSetDevice(prev);
   return QDWF_OK;

@@ -96,10 +96,12 @@ _SIG = {
     "qdwf_tuned_shape": ([_P, _I, _I, _I, _I, _P], _I),
     "qdwf_request_bytes": ([ctypes.POINTER(qdwf_action), ctypes.POINTER(qdwf_solve_params)],
                            ctypes.c_size_t),
-    "qdwf_pool_create": ([_I, ctypes.c_size_t, _I, ctypes.POINTER(_P)], _I),
+    "qdwf_pool_overhead_bytes": ([_I], ctypes.c_size_t),
+    "qdwf_pool_create": ([_I, _P, ctypes.c_size_t, _I, ctypes.POINTER(qdwf_solve_params),
+                          ctypes.POINTER(_P)], _I),
     "qdwf_pool_destroy": ([_P], _I),
     "qdwf_pool_submit": ([_P, ctypes.POINTER(qdwf_request), ctypes.POINTER(ctypes.c_uint64)], _I),
-    "qdwf_pool_step": ([_P, ctypes.POINTER(_I)], _I),
+    "qdwf_pool_step": ([_P, _P, ctypes.POINTER(_I)], _I),
     "qdwf_pool_poll": ([_P, ctypes.c_uint64, ctypes.POINTER(qdwf_solve_stats)], _I),
     "qdwf_pool_info": ([_P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t),
                         ctypes.POINTER(_I), ctypes.POINTER(_I)], _I),
@@ -328,10 +330,18 @@ def qdwf_request_bytes(act: qdwf_action, params: qdwf_solve_params) -> int:
     return int(lib().qdwf_request_bytes(ctypes.byref(act), ctypes.byref(params)))
 
 
-def qdwf_pool_create(device: int, hbm_budget: int, max_slots: int):
+def qdwf_pool_overhead_bytes(max_slots: int) -> int:
+    return int(lib().qdwf_pool_overhead_bytes(int(max_slots)))
+
+
+def qdwf_pool_create(device: int, arena: torch.Tensor, max_slots: int,
+                     params: qdwf_solve_params):
+    """The arena (a uint8 CUDA tensor, 256-byte aligned) is the pool's whole
+    device memory; the caller keeps it alive until qdwf_pool_destroy."""
     h = ctypes.c_void_p()
-    _check(lib().qdwf_pool_create(int(device), ctypes.c_size_t(int(hbm_budget)), int(max_slots),
-                                  ctypes.byref(h)))
+    nbytes = arena.numel() * arena.element_size()
+    _check(lib().qdwf_pool_create(int(device), _ptr(arena, "arena"), ctypes.c_size_t(nbytes),
+                                  int(max_slots), ctypes.byref(params), ctypes.byref(h)))
     return h
 
 
@@ -349,9 +359,9 @@ def qdwf_pool_submit(pool, act: qdwf_action, U, b, x_out, params: qdwf_solve_par
     return int(rid.value)
 
 
-def qdwf_pool_step(pool) -> int:
+def qdwf_pool_step(pool, stream=None) -> int:
     n = ctypes.c_int()
-    _check(lib().qdwf_pool_step(pool, ctypes.byref(n)))
+    _check(lib().qdwf_pool_step(pool, _stream(stream), ctypes.byref(n)))
     return int(n.value)
 
 

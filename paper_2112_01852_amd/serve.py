@@ -88,12 +88,14 @@ class Prepared:
     x: torch.Tensor = field(default=None)
 
 
-def prepare(specs, device="cuda"):
+def prepare(specs, device="cuda", with_x: bool = True):
+    """Links and source of every request on the GPU (and a zeroed solution
+    buffer each when with_x)."""
     out = []
     for sp in specs:
         U = smoothed_gauge_torch(sp.L, sp.link_seed, device=device)
         b = gaussian_source_torch(sp.L, sp.Ls, sp.src_seed, device=device)
-        out.append(Prepared(sp, U, b, torch.zeros_like(b)))
+        out.append(Prepared(sp, U, b, torch.zeros_like(b) if with_x else None))
     torch.cuda.synchronize()
     return out
 
@@ -122,25 +124,39 @@ def poisson_arrivals(n: int, rate: float, seed: int):
     return np.cumsum(rng.exponential(1.0 / rate, size=n))
 
 
-def run_pool(prepared, arrivals, params, budget_bytes: int, max_slots: int, device: int = 0):
-    """Drive the pool in real time: submit each request at its arrival time,
-    step, poll. Returns per-request latency (completion - arrival), statuses,
-    stats and the pool's peak footprint."""
-    pool = q.qdwf_pool_create(device, budget_bytes, max_slots)
+def run_pool(prepared, arrivals, params, arena_bytes: int, max_slots: int, device: int = 0,
+             keep_x: bool = True):
+    """Drive a pool in real time on torch's current stream: submit each
+    request at its arrival time, step, poll. The pool's whole device memory
+    is one arena tensor of arena_bytes. Returns per-request latency
+    (completion - arrival), statuses, stats, the pool's peak arena use, the
+    makespan and the device memory the process lost between the first and the
+    last step (the pool allocates none after creation). keep_x: leave each
+    solution in its request's x buffer (otherwise the buffer is released
+    after the request finishes)."""
     n = len(prepared)
+    arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=torch.device("cuda", device))
+    pool = q.qdwf_pool_create(device, arena, max_slots, params)
     ids = [None] * n
     done_at = [None] * n
     status = [None] * n
     stats = [None] * n
+    xbuf = [None] * n
+    torch.cuda.synchronize(device)
+    free0 = torch.cuda.mem_get_info(device)[0]
+    free_min = free0
     t0 = time.perf_counter()
     nxt = 0
     finished = 0
+    pending = []
     try:
         while finished < n:
             now = time.perf_counter() - t0
             while nxt < n and arrivals[nxt] <= now:
                 p = prepared[nxt]
-                ids[nxt] = q.qdwf_pool_submit(pool, p.spec.action(), p.U, p.b, p.x, params)
+                xbuf[nxt] = p.x if keep_x else torch.empty_like(p.b)
+                ids[nxt] = q.qdwf_pool_submit(pool, p.spec.action(), p.U, p.b, xbuf[nxt], params)
+                pending.append(nxt)
                 nxt += 1
             info = q.qdwf_pool_info(pool)
             if info["active"] == 0 and info["queued"] == 0:
@@ -149,31 +165,29 @@ def run_pool(prepared, arrivals, params, budget_bytes: int, max_slots: int, devi
                 continue
             q.qdwf_pool_step(pool)
             now = time.perf_counter() - t0
-            for i in range(nxt):
-                if ids[i] is not None and done_at[i] is None:
-                    ok, rc, st = q.qdwf_pool_poll(pool, ids[i])
-                    if ok:
-                        done_at[i] = now
-                        status[i] = rc
-                        stats[i] = st.as_dict()
-                        finished += 1
-        peak = q.qdwf_pool_info(pool)["peak"]
+            still = []
+            for i in pending:
+                ok, rc, st = q.qdwf_pool_poll(pool, ids[i])
+                if ok:
+                    done_at[i] = now
+                    status[i] = rc
+                    stats[i] = st.as_dict()
+                    finished += 1
+                    if not keep_x:
+                        xbuf[i] = None
+                else:
+                    still.append(i)
+            pending = still
+            free_min = min(free_min, torch.cuda.mem_get_info(device)[0])
+        torch.cuda.synchronize(device)
+        info = q.qdwf_pool_info(pool)
     finally:
         q.qdwf_pool_destroy(pool)
+        del arena
     lat = np.array(done_at) - np.array(arrivals)
-    return {"latency": lat, "status": status, "stats": stats, "peak_bytes": peak,
-            "makespan": float(max(done_at))}
-
-
-def fifo_baseline(service_times, arrivals):
-    """Single-server FIFO queue with the given service times (plain solves one
-    at a time in arrival order): latency = completion - arrival."""
-    t = 0.0
-    lat = []
-    for a, s in zip(arrivals, service_times):
-        t = max(t, a) + s
-        lat.append(t - a)
-    return np.array(lat), t
+    return {"latency": lat, "status": status, "stats": stats, "peak_bytes": info["peak"],
+            "in_use_end": info["in_use"], "makespan": float(max(done_at)),
+            "device_bytes_taken_while_serving": int(free0 - free_min)}
 
 
 def percentiles(lat):

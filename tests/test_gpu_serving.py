@@ -1,9 +1,16 @@
-"""Serving pool: continuous batching of heterogeneous solves.
+"""Serving pool: continuous batching of heterogeneous solves through grouped
+launches, in a caller-provided arena.
 
-Each served result must equal the same request solved alone (bitwise: the
-per-request arithmetic and round schedule do not depend on the batch), every
-solve must reach the FP64 true residual, and the pool must never hold more
-than its HBM budget.
+Every served result must
+* equal, bit for bit, the same request served alone (a pool holding only it),
+* agree with qdwf_solve on the same request to 1e-8 relative (bitwise
+  equality is expected and recorded: the same kernel bodies, reduction trees
+  and iteration sequence),
+* reach an FP64 true residual <= 1e-10, recomputed here with the oracle's
+  M_pc on the request's own links, mass and source (<= 1.5e-10),
+and the pool must stay inside its arena: its own accounting never exceeds the
+arena, and the device memory free to the process does not shrink while it
+serves (it allocates nothing after creation).
 """
 import numpy as np
 import pytest
@@ -26,25 +33,7 @@ def _specs(serve):
     S = serve.Spec
     return [S((4, 4, 4, 4), 8, 0.05, 11, 12), S((4, 4, 4, 6), 12, 0.01, 13, 14),
             S((6, 6, 6, 6), 8, 0.003, 15, 16), S((4, 4, 4, 4), 16, 0.1, 17, 18),
-            S((8, 8, 8, 8), 8, 0.02, 19, 20)]
-
-
-def test_served_equals_alone_and_respects_budget(env):
-    q, serve, torch = env
-    params = q.solve_params(inner_prec=q.QDWF_F32, layout=q.QDWF_RIRI, tol=1e-10, check_every=4)
-    prepared = serve.prepare(_specs(serve))
-    sizes = [q.qdwf_request_bytes(p.spec.action(), params) for p in prepared]
-    budget = sorted(sizes)[-1] + sorted(sizes)[-2]      # at most two big ones at a time
-    arrivals = np.zeros(len(prepared))                   # all at once: exercises the queue
-    res = serve.run_pool(prepared, arrivals, params, budget, max_slots=3)
-    assert res["peak_bytes"] <= budget
-    for i, p in enumerate(prepared):
-        assert res["status"][i] == q.QDWF_OK
-        assert res["stats"][i]["true_residual"] <= 1e-10
-        rc, st, dt, alone = serve.solo_solve(p, params)
-        assert rc == q.QDWF_OK
-        assert torch.equal(p.x, alone), f"request {i} differs between served and alone"
-        assert _oracle_residual(p) <= 1.5e-10, i
+            S((8, 8, 8, 8), 16, 0.02, 19, 20)]
 
 
 def _oracle_residual(p):
@@ -60,30 +49,126 @@ def _oracle_residual(p):
     return float(np.linalg.norm(r) / np.linalg.norm(b))
 
 
-def test_mixed_inner_precisions_converge(env):
+def _tables_subset_sums(prepared):
+    """Possible arena bytes of the site tables the pool may still keep after
+    serving: any subset of the lattice shapes served (tables nobody uses are
+    evicted when the arena needs the room). Per shape: neighbours [2][8][V/2],
+    site order [2][V/2] and index [V], int32, each rounded to 256 bytes."""
+    import itertools
+    al = lambda b: (b + 255) // 256 * 256
+    per = []
+    for L in {p.spec.L for p in prepared}:
+        V = int(np.prod(L))
+        per.append(al(4 * 2 * 8 * (V // 2)) + al(4 * V) + al(4 * V))
+    return {sum(c) for r in range(len(per) + 1) for c in itertools.combinations(per, r)}
+
+
+def _arena_for(q, prepared, params, slots, n_big):
+    sizes = sorted(q.qdwf_request_bytes(p.spec.action(), params) for p in prepared)
+    return q.qdwf_pool_overhead_bytes(slots) + sum(sizes[-n_big:])
+
+
+@pytest.mark.parametrize("inner", [1, 2])
+def test_served_equals_alone_and_solo_and_oracle(env, inner):
+    q, serve, torch = env
+    params = q.solve_params(inner_prec=inner, layout=q.QDWF_RIRI, tol=1e-10, check_every=4)
+    prepared = serve.prepare(_specs(serve))
+    arena = _arena_for(q, prepared, params, 3, 2)    # at most two big ones at a time
+    print(f"mix of {len(prepared)} requests, inner {q.PREC_NAME[inner]}, arena {arena} bytes",
+          flush=True)
+    res = serve.run_pool(prepared, np.zeros(len(prepared)), params, arena, max_slots=3)
+    assert res["peak_bytes"] <= arena
+    # what stays in use: the pool's own table and states, and the site tables
+    # it still keeps for lattice shapes it has served; every request's own
+    # memory has been returned
+    kept = res["in_use_end"] - q.qdwf_pool_overhead_bytes(3)
+    assert kept in _tables_subset_sums(prepared), kept
+    print(f"  device bytes taken while serving: {res['device_bytes_taken_while_serving']}",
+          flush=True)
+    assert res["device_bytes_taken_while_serving"] <= 16 << 20
+    mixed = [p.x.clone() for p in prepared]
+    for i, p in enumerate(prepared):
+        assert res["status"][i] == q.QDWF_OK, i
+        assert res["stats"][i]["true_residual"] <= 1e-10
+        # alone: a pool holding only this request
+        p.x.zero_()
+        one = serve.run_pool([p], np.zeros(1), params,
+                             q.qdwf_pool_overhead_bytes(1)
+                             + q.qdwf_request_bytes(p.spec.action(), params), max_slots=1)
+        assert one["status"][0] == q.QDWF_OK
+        assert torch.equal(p.x, mixed[i]), f"request {i} differs between the mix and alone"
+        # qdwf_solve on the same request
+        rc, st, dt, solo = serve.solo_solve(p, params)
+        assert rc == q.QDWF_OK
+        rel = float(torch.linalg.vector_norm(solo - p.x) / torch.linalg.vector_norm(solo))
+        print(f"  request {i}: served vs qdwf_solve rel {rel:.3e} bitwise {torch.equal(solo, p.x)}",
+              flush=True)
+        assert rel <= 1e-8, (i, rel)
+        assert _oracle_residual(p) <= 1.5e-10, i
+
+
+def test_bf16_and_fp64_pools_converge(env):
     q, serve, torch = env
     prepared = serve.prepare(_specs(serve)[:3])
-    for inner in (q.QDWF_F16, q.QDWF_BF16):
+    for inner in (q.QDWF_BF16, q.QDWF_F64):
         params = q.solve_params(inner_prec=inner, tol=1e-10, check_every=8)
-        budget = sum(q.qdwf_request_bytes(p.spec.action(), params) for p in prepared)
-        res = serve.run_pool(prepared, np.zeros(3), params, budget, max_slots=4)
+        arena = _arena_for(q, prepared, params, 4, 3)
+        res = serve.run_pool(prepared, np.zeros(3), params, arena, max_slots=4)
         for i in range(3):
             assert res["status"][i] == q.QDWF_OK
             assert res["stats"][i]["true_residual"] <= 1e-10
             assert _oracle_residual(prepared[i]) <= 1.5e-10, (inner, i)
 
 
-def test_pool_rejects_what_can_never_fit_and_unknown_ids(env):
+def test_staggered_arrivals_and_slot_reuse(env):
+    """Requests arriving while others run join the next round; one slot is
+    reused many times; results still match the oracle."""
+    q, serve, torch = env
+    params = q.solve_params(inner_prec=q.QDWF_F32, tol=1e-10, check_every=2)
+    prepared = serve.prepare(_specs(serve)[:4])
+    arena = _arena_for(q, prepared, params, 2, 2)
+    res = serve.run_pool(prepared, np.array([0.0, 0.0, 0.002, 0.004]), params, arena, max_slots=2)
+    for i, p in enumerate(prepared):
+        assert res["status"][i] == q.QDWF_OK
+        assert _oracle_residual(p) <= 1.5e-10, i
+
+
+def test_not_converged_is_reported(env):
+    q, serve, torch = env
+    params = q.solve_params(inner_prec=q.QDWF_F32, tol=1e-10, max_iter=5, check_every=4)
+    p = serve.prepare(_specs(serve)[4:5])[0]
+    arena = _arena_for(q, [p], params, 1, 1)
+    res = serve.run_pool([p], np.zeros(1), params, arena, max_slots=1)
+    assert res["status"][0] == q.QDWF_ENOTCONV
+    st = res["stats"][0]
+    assert st["iterations"] == 5 and st["true_residual"] > 1e-10
+
+
+def test_pool_rejects_what_can_never_fit_and_bad_requests(env):
     q, serve, torch = env
     params = q.solve_params(inner_prec=q.QDWF_F32, tol=1e-10)
     p = serve.prepare(_specs(serve)[:1])[0]
     need = q.qdwf_request_bytes(p.spec.action(), params)
-    pool = q.qdwf_pool_create(0, need - 1, 2)
+    over = q.qdwf_pool_overhead_bytes(2)
+    small = torch.empty(over - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(q.QdwfError) as e:
+        q.qdwf_pool_create(0, small, 2, params)
+    assert e.value.code == q.QDWF_EINVAL
+    arena = torch.empty(over + need - 256, dtype=torch.uint8, device="cuda")
+    pool = q.qdwf_pool_create(0, arena, 2, params)
     try:
         with pytest.raises(q.QdwfError) as e:
             q.qdwf_pool_submit(pool, p.spec.action(), p.U, p.b, p.x, params)
         assert e.value.code == q.QDWF_EINVAL
+        other = q.solve_params(inner_prec=q.QDWF_F16, tol=1e-10)
+        with pytest.raises(q.QdwfError):
+            q.qdwf_pool_submit(pool, p.spec.action(), p.U, p.b, p.x, other)
+        bad_ls = q.make_action((4, 4, 4, 4), 4, mf=0.01, M5=1.8, b=1.5, c=0.5)
+        with pytest.raises(q.QdwfError):
+            q.qdwf_pool_submit(pool, bad_ls, p.U, p.b, p.x, params)
         with pytest.raises(q.QdwfError):
             q.qdwf_pool_poll(pool, 12345)
+        info = q.qdwf_pool_info(pool)
+        assert info["in_use"] == over and info["queued"] == 0
     finally:
         q.qdwf_pool_destroy(pool)
