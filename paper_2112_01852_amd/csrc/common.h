@@ -98,7 +98,9 @@ struct Geom {
 };
 
 // 5D-local chiral matrices (Ls x Ls per chirality) kept on device.
-enum MatKind { MAT_MEE = 0, MAT_MEE_DAG, MAT_MEEINV, MAT_MEEINV_DAG, MAT_COUNT };
+// MAT_AMEEINV = (A/b) M_ee^-1 = (1 + (c/b) C) M_ee^-1: the first stage of M_pc
+// hands the second its input with A already applied.
+enum MatKind { MAT_MEE = 0, MAT_MEE_DAG, MAT_MEEINV, MAT_MEEINV_DAG, MAT_AMEEINV, MAT_COUNT };
 
 // Launch shape of the hop kernel, chosen per (precision, layout, nrhs) by
 // the tuner or by the default rule.
@@ -217,6 +219,8 @@ struct HopArgs {
   int nrhs;
   int epi;
   int minv;   // 1: apply M_ee^-1 (M_ee^-dag when dagger) to the result; Ls = 16, epi = 0
+  int chi;    // D_h only (dagger = 0): without minv, in holds (A/b) in, which the hop
+              // takes as it is; with minv, the result is multiplied by A/b
   double hop_scale, alpha, beta;
   const void* links;   // links to use instead of the context's (nullptr: the context's)
 };

@@ -90,7 +90,7 @@ template <class S, bool DPP16> struct GroupWaves {
   static constexpr int v = sizeof(S) == 8 ? 1 : (sizeof(S) == 2 && !DPP16) ? 2 : WavesPerEU<S>::v;
 };
 
-template <class S, int LAYOUT, bool DAG, bool DPP16, bool MINV>
+template <class S, int LAYOUT, bool DAG, bool DPP16, bool MINV, bool CHI>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(GroupWaves<S, DPP16>::v, GroupWaves<S, DPP16>::v)))
 g_hop(const Table* __restrict__ t, int stage, int fp64, int want) {
@@ -101,7 +101,7 @@ g_hop(const Table* __restrict__ t, int stage, int fp64, int want) {
   for (int u = blockIdx.x; u < total; u += gridDim.x) {
     const int j = member_of(h, u);
     if (t->req[j].st->status != want) continue;
-    hop_block<S, LAYOUT, DAG, DPP16, MINV>(tab[j], u - h.start[j], smem);
+    hop_block<S, LAYOUT, DAG, DPP16, MINV, CHI>(tab[j], u - h.start[j], smem);
     __syncthreads();
   }
 }
@@ -265,16 +265,18 @@ int record_round(const Table* t, int k, hipStream_t st) {
       og(kGroupMax);
   auto mdagm = [&](auto stag, size_t lds, size_t llds, int fp64, int want) {
     typedef decltype(stag) P;
-    hipLaunchKernelGGL((g_hop<P, LAYOUT, false, true, true>), hg, hb, lds, st, t, 0, fp64, want);
-    hipLaunchKernelGGL((g_hop<P, LAYOUT, false, false, false>), hg, hb, lds, st, t, 0, fp64, want);
+    // M_pc: its first stage hands the second chi = (A/b) M_ee^-1 M_eo p
+    hipLaunchKernelGGL((g_hop<P, LAYOUT, false, true, true, true>), hg, hb, lds, st, t, 0, fp64, want);
+    hipLaunchKernelGGL((g_hop<P, LAYOUT, false, false, false, false>), hg, hb, lds, st, t, 0, fp64, want);
     hipLaunchKernelGGL((g_local<P, LAYOUT>), lg, lb, llds, st, t, 0, fp64, want);
-    hipLaunchKernelGGL((g_hop<P, LAYOUT, false, true, false>), hg, hb, lds, st, t, 1, fp64, want);
-    hipLaunchKernelGGL((g_hop<P, LAYOUT, false, false, false>), hg, hb, lds, st, t, 1, fp64, want);
-    hipLaunchKernelGGL((g_hop<P, LAYOUT, true, true, true>), hg, hb, lds, st, t, 2, fp64, want);
-    hipLaunchKernelGGL((g_hop<P, LAYOUT, true, false, false>), hg, hb, lds, st, t, 2, fp64, want);
+    hipLaunchKernelGGL((g_hop<P, LAYOUT, false, true, false, true>), hg, hb, lds, st, t, 1, fp64, want);
+    hipLaunchKernelGGL((g_hop<P, LAYOUT, false, false, false, true>), hg, hb, lds, st, t, 1, fp64, want);
+    // M_pc^dag
+    hipLaunchKernelGGL((g_hop<P, LAYOUT, true, true, true, false>), hg, hb, lds, st, t, 2, fp64, want);
+    hipLaunchKernelGGL((g_hop<P, LAYOUT, true, false, false, false>), hg, hb, lds, st, t, 2, fp64, want);
     hipLaunchKernelGGL((g_local<P, LAYOUT>), lg, lb, llds, st, t, 1, fp64, want);
-    hipLaunchKernelGGL((g_hop<P, LAYOUT, true, true, false>), hg, hb, lds, st, t, 3, fp64, want);
-    hipLaunchKernelGGL((g_hop<P, LAYOUT, true, false, false>), hg, hb, lds, st, t, 3, fp64, want);
+    hipLaunchKernelGGL((g_hop<P, LAYOUT, true, true, false, false>), hg, hb, lds, st, t, 3, fp64, want);
+    hipLaunchKernelGGL((g_hop<P, LAYOUT, true, false, false, false>), hg, hb, lds, st, t, 3, fp64, want);
   };
   for (int i = 0; i < k; ++i) {
     // reliable update of the members that asked for one (and the initial one)
@@ -350,11 +352,12 @@ int fill_mdagm(qdwf_ctx* ctx, int prec, const void* in, void* out, void* v, void
     a.nrhs = 1;
     a.hop_scale = -0.5;
     a.minv = ls16 ? 1 : 0;
+    a.chi = (ls16 && !dag) ? 1 : 0;
     if ((rc = fill_hop(ctx, prec, a, hk[2 * dag]))) return rc;
     GLoc& l = *lk[dag];
     l.in = te1;
     l.out = te2;
-    const MatKind kind = dag ? MAT_MEEINV_DAG : MAT_MEEINV;
+    const MatKind kind = dag ? MAT_MEEINV_DAG : MAT_AMEEINV;
     const size_t off = (size_t)kind * 2 * g.Ls * g.Ls;
     l.K = prec == QDWF_F64 ? (const void*)(ctx->d_mat64 + off) : (const void*)(ctx->d_mat32 + off);
     l.Vh = g.Vh;
@@ -372,6 +375,7 @@ int fill_mdagm(qdwf_ctx* ctx, int prec, const void* in, void* out, void* v, void
     b.hop_scale = 0.5;
     b.alpha = al;
     b.beta = be;
+    b.chi = dag ? 0 : 1;
     if ((rc = fill_hop(ctx, prec, b, hk[2 * dag + 1]))) return rc;
   }
   return QDWF_OK;

@@ -9,34 +9,45 @@ namespace qdwf {
 
 namespace {
 
-template <class S, int LAYOUT, bool DAG, bool DPP16, bool MINV>
+template <class S, int LAYOUT, bool DAG, bool DPP16, bool MINV, bool CHI>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_kernel(HopK k) {
   extern __shared__ __align__(16) unsigned char smem[];
   // the XCD remap hands each XCD a contiguous range of logical blocks
   const int L = k.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
-  hop_block<S, LAYOUT, DAG, DPP16, MINV>(k, L, smem);
+  hop_block<S, LAYOUT, DAG, DPP16, MINV, CHI>(k, L, smem);
 }
 
-template <class S, int LAYOUT, bool DAG, bool DPP16, bool MINV>
+template <class S, int LAYOUT, bool DAG, bool DPP16, bool MINV, bool CHI>
 int run_hop_k(qdwf_ctx* ctx, int prec, const HopArgs& a, hipStream_t st, const HopShape& sh) {
   HopK k;
   size_t lds = 0;
   int nb = 0;
   int rc = make_hopk<S, MINV>(ctx, prec, a, sh, &k, &lds, &nb);
   if (rc) return rc;
-  hipLaunchKernelGGL((hop_kernel<S, LAYOUT, DAG, DPP16, MINV>), dim3(nb), dim3(sh.threads), lds, st, k);
+  hipLaunchKernelGGL((hop_kernel<S, LAYOUT, DAG, DPP16, MINV, CHI>), dim3(nb), dim3(sh.threads), lds,
+                     st, k);
   QDWF_HIP(hipGetLastError());
   return QDWF_OK;
 }
 
 template <class S, int LAYOUT, bool DAG>
 int run_hop(qdwf_ctx* ctx, int prec, const HopArgs& a, hipStream_t st, const HopShape& sh) {
+  if (a.chi && DAG) return fail(QDWF_EINVAL, "the adjoint hop takes no A-applied input");
+  if constexpr (!DAG) {
+    if (a.chi) {
+      if (ctx->g.Ls == 16)
+        return a.minv ? run_hop_k<S, LAYOUT, false, true, true, true>(ctx, prec, a, st, sh)
+                      : run_hop_k<S, LAYOUT, false, true, false, true>(ctx, prec, a, st, sh);
+      if (a.minv) return fail(QDWF_EINVAL, "fused M_ee^-1 needs Ls = 16");
+      return run_hop_k<S, LAYOUT, false, false, false, true>(ctx, prec, a, st, sh);
+    }
+  }
   if (ctx->g.Ls == 16)
-    return a.minv ? run_hop_k<S, LAYOUT, DAG, true, true>(ctx, prec, a, st, sh)
-                  : run_hop_k<S, LAYOUT, DAG, true, false>(ctx, prec, a, st, sh);
+    return a.minv ? run_hop_k<S, LAYOUT, DAG, true, true, false>(ctx, prec, a, st, sh)
+                  : run_hop_k<S, LAYOUT, DAG, true, false, false>(ctx, prec, a, st, sh);
   if (a.minv) return fail(QDWF_EINVAL, "fused M_ee^-1 needs Ls = 16");
-  return run_hop_k<S, LAYOUT, DAG, false, false>(ctx, prec, a, st, sh);
+  return run_hop_k<S, LAYOUT, DAG, false, false, false>(ctx, prec, a, st, sh);
 }
 
 }  // namespace

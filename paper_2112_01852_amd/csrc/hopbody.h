@@ -20,8 +20,11 @@
 //     multiplied per direction (Table 3 counts this as 1320 flops per site).
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 #include "hopcore.h"
+#include "pk16.h"
 #include "siteio.h"
 #include "spin.h"
 
@@ -48,11 +51,20 @@ template <class S> struct WavesPerEU { static constexpr int v = sizeof(S) >= 4 ?
 
 // One block's share of a hop launch: logical block L of the launch described
 // by k (its sites, parity and right-hand sides), with smem the block's LDS
-// (the LDS bytes make_hopk reports). Every 5D site's result depends only on k and the site, not
-// on which block or launch computes it.
-template <class S, int LAYOUT, bool DAG, bool DPP16, bool MINV>
+// (the LDS bytes make_hopk reports). Every 5D site's result depends only on
+// k and the site, not on which block or launch computes it.
+// CHI (D_h only, not the adjoint): without MINV the input already holds
+// chi = (A/b) psi, so the hop takes it as it is; with MINV the result is
+// multiplied by A/b after M_ee^-1 (the two commute: both are functions of
+// C), so that the next hop of M_pc can take it as chi.
+// FP16 storage in the interleaved layout takes the packed path (pk16.h):
+// neighbour spinors stay packed, half spinors are projected in packed FP16
+// and multiplied with v_dot2_f32_f16 into FP32.
+template <class S, int LAYOUT, bool DAG, bool DPP16, bool MINV, bool CHI = false>
 __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
   typedef typename Store<S>::compute T;
+  static_assert(!(DAG && CHI), "the adjoint hop applies A^dag once per site");
+  constexpr bool PK = std::is_same<S, _Float16>::value && LAYOUT == QDWF_RIRI;
   constexpr int LSTR = LinkStride<T>::v;
   T* su = reinterpret_cast<T*>(smem);                       // [nsb][8][LSTR]
   int* snb = reinterpret_cast<int*>(su + (size_t)8 * LSTR * k.nsb);   // [8][nsb]
@@ -94,12 +106,34 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
   const S* in = reinterpret_cast<const S*>(k.in[p]) + (long)rc * k.rs_in;
   const int* nbs = snb + sl;
 
-  T va[24], vb[24];   // two neighbour spinors in flight
-  SiteIO<S, LAYOUT>::load(in, nbs[0], s, Ls, k.plane, va);
-  SiteIO<S, LAYOUT>::load(in, nbs[k.nsb], s, Ls, k.plane, vb);
+  // two neighbour spinors in flight (packed path: 12 words each)
+  T va[24], vb[24];
+  uint32_t wa[12], wb[12];
+  // a site's 24 reals as 12 (re, im) FP16 words, in the order of SiteIO
+  auto load_pk = [&](int site, uint32_t* w) {
+    long i = site;
+    int ss = s, lsb = Ls;
+    riri_block(i, ss, lsb);
+    const uint2* pp = reinterpret_cast<const uint2*>(in + i * lsb * 24 + (long)ss * 4);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      const uint2 qq = pp[c * lsb];
+      w[2 * c] = qq.x;
+      w[2 * c + 1] = qq.y;
+    }
+  };
+  if constexpr (PK) {
+    load_pk(nbs[0], wa);
+    load_pk(nbs[k.nsb], wb);
+  } else {
+    SiteIO<S, LAYOUT>::load(in, nbs[0], s, Ls, k.plane, va);
+    SiteIO<S, LAYOUT>::load(in, nbs[k.nsb], s, Ls, k.plane, vb);
+  }
 
   {
     // one thread per link: 18 contiguous reals, loaded with vector loads
+    // (packed path: 9 (re, im) words, staged in the two sign-adjusted forms
+    // of link_words)
     const S* lk = reinterpret_cast<const S*>(k.links);
     const int nlink = 8 * k.nsb;
     for (int i = threadIdx.x; i < nlink; i += blockDim.x) {
@@ -108,11 +142,22 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
       int par, site;
       if (d < 4) { par = p; site = min(cb0 + sl2, Vh - 1); }
       else       { par = q; site = snb[d * k.nsb + sl2]; }
-      T Ul[18];
-      LinkIO<S>::load(lk + (((long)par * 4 + mu) * Vh + site) * 18, Ul);
-      T* dstp = su + (sl2 * 8 + d) * LSTR;
+      const S* src = lk + (((long)par * 4 + mu) * Vh + site) * 18;
+      if constexpr (PK) {
+        const uint32_t* qw = reinterpret_cast<const uint32_t*>(src);
+        uint32_t* dstw = reinterpret_cast<uint32_t*>(su + (sl2 * 8 + d) * LSTR);
+        uint32_t w[9];
 #pragma unroll
-      for (int c = 0; c < 18; ++c) dstp[c] = Ul[c];
+        for (int c = 0; c < 9; ++c) w[c] = qw[c];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) link_words(w[c], d < 4, &dstw[c], &dstw[9 + c]);
+      } else {
+        T Ul[18];
+        LinkIO<S>::load(src, Ul);
+        T* dstp = su + (sl2 * 8 + d) * LSTR;
+#pragma unroll
+        for (int c = 0; c < 18; ++c) dstp[c] = Ul[c];
+      }
     }
   }
   __syncthreads();
@@ -138,23 +183,66 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
     constexpr bool FWD = D < 4;
     // (1 - g) on forward hops and (1 + g) on backward ones; swapped for D_h^dag
     constexpr int SG = (FWD != DAG) ? -1 : +1;
-    T* buf = (D & 1) ? vb : va;
-    T v[24];
+    // chi / b = psi + (c/b) (P+ psi_{s-1} + P- psi_{s+1}), walls included,
+    // unless the input already holds it (CHI without MINV) or the hop is the
+    // adjoint's
+    constexpr bool APPLY_A = !DAG && !(CHI && !MINV);
+    T uh[12];
+    if constexpr (PK) {
+      uint32_t* buf = (D & 1) ? wb : wa;
+      uint32_t w[12];
 #pragma unroll
-    for (int i = 0; i < 24; ++i) v[i] = buf[i];
-    if constexpr (D < 6)
-      SiteIO<S, LAYOUT>::load(in, nbs[(D + 2) * k.nsb], s, Ls, k.plane, buf);
-    if constexpr (!DAG) {
-      // chi / b = psi + (c/b) (P+ psi_{s-1} + P- psi_{s+1}), walls included
-      T w[24];
+      for (int i = 0; i < 12; ++i) w[i] = buf[i];
+      if constexpr (D < 6) load_pk(nbs[(D + 2) * k.nsb], buf);
+      uint32_t h[6];
+      if constexpr (APPLY_A) {
+        T v[24], x[24];
 #pragma unroll
-      for (int i = 0; i < 24; ++i) w[i] = v[i];
-      shift_s<1, 15>(sh, cm, cp, w, v);
+        for (int i = 0; i < 12; ++i) {
+          v[2 * i] = f16_lo(w[i]);
+          v[2 * i + 1] = f16_hi(w[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < 24; ++i) x[i] = v[i];
+        shift_s<1, 15>(sh, cm, cp, x, v);
+        T hf[12];
+        project<MU, SG>(v, hf);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) h[i] = pk_f16(hf[2 * i], hf[2 * i + 1]);
+      } else {
+        project_pk<MU, SG>(w, h);
+      }
+      const uint32_t* lw = reinterpret_cast<const uint32_t*>(lks + D * LSTR);
+      uint32_t U[18];
+      {
+        const uint4* q4 = reinterpret_cast<const uint4*>(lw);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint4 t4 = q4[j];
+          U[4 * j] = t4.x; U[4 * j + 1] = t4.y; U[4 * j + 2] = t4.z; U[4 * j + 3] = t4.w;
+        }
+        const uint2 t2 = reinterpret_cast<const uint2*>(lw)[8];
+        U[16] = t2.x; U[17] = t2.y;
+      }
+      su3_mul_pk<!FWD>(U, U + 9, h, uh);
+    } else {
+      T* buf = (D & 1) ? vb : va;
+      T v[24];
+#pragma unroll
+      for (int i = 0; i < 24; ++i) v[i] = buf[i];
+      if constexpr (D < 6)
+        SiteIO<S, LAYOUT>::load(in, nbs[(D + 2) * k.nsb], s, Ls, k.plane, buf);
+      if constexpr (APPLY_A) {
+        T w[24];
+#pragma unroll
+        for (int i = 0; i < 24; ++i) w[i] = v[i];
+        shift_s<1, 15>(sh, cm, cp, w, v);
+      }
+      T h[12], U[18];
+      load_link(lks + D * LSTR, U);
+      project<MU, SG>(v, h);
+      su3_mul<!FWD>(U, h, uh);
     }
-    T h[12], uh[12], U[18];
-    load_link(lks + D * LSTR, U);
-    project<MU, SG>(v, h);
-    su3_mul<!FWD>(U, h, uh);
     recon_acc<MU, SG, D == 0>(uh, acc);
   };
   step(IC<0>()); step(IC<1>()); step(IC<2>()); step(IC<3>());
@@ -192,6 +280,13 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
       };
       scan(IC<0>()); scan(IC<1>()); scan(IC<2>()); scan(IC<3>());
     }
+    if constexpr (CHI) {
+      // chi / b of the result for the next hop: (1 + (c/b) C) M_ee^-1 h
+      T tmp[24];
+#pragma unroll
+      for (int i = 0; i < 24; ++i) tmp[i] = acc[i];
+      shift_s<1, 15>(sh, cm, cp, tmp, acc);
+    }
   }
   const T hs = (T)k.hop_scale_b;   // hop scale times b (and the M_ee^-1 factor)
   if (k.epi) {
@@ -210,7 +305,17 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
   }
   if (active) {
     S* out = reinterpret_cast<S*>(k.out[p]) + (long)rc * k.rs_out;
-    SiteIO<S, LAYOUT>::store(out, cbc, s, Ls, k.plane, acc);
+    if constexpr (PK) {
+      long i = cbc;
+      int ss = s, lsb = Ls;
+      riri_block(i, ss, lsb);
+      uint2* pp = reinterpret_cast<uint2*>(out + i * lsb * 24 + (long)ss * 4);
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        pp[c * lsb] = make_uint2(pk_f16(acc[4 * c], acc[4 * c + 1]), pk_f16(acc[4 * c + 2], acc[4 * c + 3]));
+    } else {
+      SiteIO<S, LAYOUT>::store(out, cbc, s, Ls, k.plane, acc);
+    }
   }
 }
 

@@ -7,6 +7,7 @@
 //   M_ee^dag   the transposes
 //   M_ee^-1    (1/alpha) sum_k rho^k S^k / (1 + mf rho^Ls), rho = -beta/alpha,
 //              with S = S_d (upper) or S_u (lower); the adjoint is its transpose.
+//   (A/b) M_ee^-1 = (1 + (c/b) S) M_ee^-1, which M_pc's first stage applies.
 // Kernel: the Ls lanes of a (site, rhs) group stage their 24 reals in LDS, then
 // each lane forms its output slice as an Ls-term sum over the staged column.
 #include <cmath>
@@ -66,6 +67,7 @@ std::vector<double> build_local_matrices(const qdwf_action& a) {
       P.swap(Q);
       rk *= rho;
     }
+    const double cob = a.c / a.b;
     for (int s = 0; s < Ls; ++s)
       for (int t = 0; t < Ls; ++t) {
         const double m = (s == t ? al : 0.0) + be * S[s * Ls + t];
@@ -73,6 +75,10 @@ std::vector<double> build_local_matrices(const qdwf_action& a) {
         at(MAT_MEE_DAG, chir, t, s) = m;
         at(MAT_MEEINV, chir, s, t) = inv[s * Ls + t];
         at(MAT_MEEINV_DAG, chir, t, s) = inv[s * Ls + t];
+        // (1 + (c/b) S) M_ee^-1 on this chirality
+        double am = inv[s * Ls + t];
+        for (int m2 = 0; m2 < Ls; ++m2) am += cob * S[s * Ls + m2] * inv[m2 * Ls + t];
+        at(MAT_AMEEINV, chir, s, t) = am;
       }
   }
   return out;

@@ -190,12 +190,18 @@ int apply_hop_parity(qdwf_ctx* ctx, int prec, int layout, int dagger, int out_pa
 }
 
 // out = M_pc in (dagger 0) or M_pc^dag in; te1, te2: even half fields.
+// For M_pc the first stage leaves chi = (A/b) M_ee^-1 M_eo in in te2 (A/b
+// and M_ee^-1 commute, both being functions of C), so the second hop takes
+// its input as it is instead of applying A to each of its 8 neighbours;
+// M_pc^dag applies A^dag once per site inside its hops anyway.
 int apply_mpc(qdwf_ctx* ctx, int prec, int layout, int dagger, void* out, const void* in,
               void* te1, void* te2, int nrhs, long rs, hipStream_t st) {
   int rc;
+  const int chi = dagger ? 0 : 1;
   if (ctx->g.Ls == 16) {
-    // te2 = M_ee^-1 M_eo in (or M_ee^-dag (M_oe)^dag in) in one launch: the
-    // hop's 16 slices of a site share a DPP row, where M_ee^-1 is a scan
+    // te2 = M_ee^-1 M_eo in (times A/b), or M_ee^-dag (M_oe)^dag in, in one
+    // launch: the hop's 16 slices of a site share a DPP row, where M_ee^-1 is
+    // a scan
     HopArgs a = {};
     a.in[QDWF_EVEN] = in;
     a.out[QDWF_EVEN] = te2;
@@ -205,18 +211,33 @@ int apply_mpc(qdwf_ctx* ctx, int prec, int layout, int dagger, void* out, const 
     a.nrhs = nrhs;
     a.hop_scale = -0.5;
     a.minv = 1;
+    a.chi = chi;
     if ((rc = launch_hop(ctx, prec, layout, dagger, a, st))) return rc;
   } else {
-    // te1 = M_eo in  (or (M_oe)^dag in), then te2 = M_ee^-1 te1
+    // te1 = M_eo in  (or (M_oe)^dag in), then te2 = (A/b) M_ee^-1 te1 (or M_ee^-dag te1)
     if ((rc = apply_hop_parity(ctx, prec, layout, dagger, QDWF_EVEN, te1, in, nullptr, -0.5, nrhs,
                                rs, st)))
       return rc;
-    if ((rc = launch_local(ctx, prec, layout, dagger ? MAT_MEEINV_DAG : MAT_MEEINV, te2, te1, 1, 0,
+    if ((rc = launch_local(ctx, prec, layout, dagger ? MAT_MEEINV_DAG : MAT_AMEEINV, te2, te1, 1, 0,
                            rs, nrhs, st)))
       return rc;
   }
   // out = M_oo in - M_oe te2 = alpha in + beta C in + 1/2 D_h A te2
-  return apply_hop_parity(ctx, prec, layout, dagger, QDWF_ODD, out, te2, in, +0.5, nrhs, rs, st);
+  // (for M_pc the hop takes chi = A te2 / b from te2)
+  HopArgs a = {};
+  a.in[QDWF_ODD] = te2;
+  a.out[QDWF_ODD] = out;
+  a.z[QDWF_ODD] = in;
+  a.rs_in = a.rs_out = a.rs_z = rs;
+  a.par0 = QDWF_ODD;
+  a.npar = 1;
+  a.nrhs = nrhs;
+  a.epi = 1;
+  a.hop_scale = 0.5;
+  a.alpha = ctx->act.b * (4.0 - ctx->act.M5) + 1.0;
+  a.beta = ctx->act.c * (4.0 - ctx->act.M5) - 1.0;
+  a.chi = chi;
+  return launch_hop(ctx, prec, layout, dagger, a, st);
 }
 
 int apply_mdagm(qdwf_ctx* ctx, int prec, int layout, void* out, const void* in, void* v,

@@ -140,10 +140,12 @@ def test_apply_Deo(case, prec, layout):
             assert _rel(got, ref) < TOL[prec]
 
 
-@pytest.mark.parametrize("prec", [0, 1, 3])
-def test_apply_Mpc_and_MdagM(case, prec):
+@pytest.mark.parametrize("prec", [0, 1, 2, 3])
+@pytest.mark.parametrize("layout", [0, 1])
+def test_apply_Mpc_and_MdagM(case, prec, layout):
+    # M_pc's second hop takes chi = (A/b) M_ee^-1 M_eo in from its first stage;
+    # FP16 in the interleaved layout runs the packed-FP16 hop
     q, D, a = case.q, case.D, case.a
-    layout = q.QDWF_RIRI
     src = cpu.restrict(case.psi, a.L, 1)
     f = D.pack(src, prec, layout, q.QDWF_ODD)
     ws = D.workspace(q.QDWF_OP_MDAGM, prec)
