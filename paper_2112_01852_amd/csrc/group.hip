@@ -86,13 +86,14 @@ __device__ inline int member_of(const UnitHdr& h, int u) {
 // form spills: FP64 takes one (its permute form needs more than the 256
 // registers two waves leave; FP64 runs only in the reliable updates), the
 // permute form of 16-bit storage two, the others as the single-context hop.
-template <class S, bool DPP16> struct GroupWaves {
-  static constexpr int v = sizeof(S) == 8 ? 1 : (sizeof(S) == 2 && !DPP16) ? 2 : WavesPerEU<S>::v;
+template <class S, int LAYOUT, bool DPP16> struct GroupWaves {
+  static constexpr int v =
+      sizeof(S) == 8 ? 1 : (sizeof(S) == 2 && !DPP16) ? 2 : WavesPerEU<S, LAYOUT, DPP16>::v;
 };
 
 template <class S, int LAYOUT, bool DAG, bool DPP16, bool MINV, bool CHI>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(GroupWaves<S, DPP16>::v, GroupWaves<S, DPP16>::v)))
+__attribute__((amdgpu_waves_per_eu(GroupWaves<S, LAYOUT, DPP16>::v, GroupWaves<S, LAYOUT, DPP16>::v)))
 g_hop(const Table* __restrict__ t, int stage, int fp64, int want) {
   extern __shared__ __align__(16) unsigned char smem[];
   const UnitHdr& h = DPP16 ? t->hop16 : t->hopg;

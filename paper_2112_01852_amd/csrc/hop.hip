@@ -11,7 +11,8 @@ namespace {
 
 template <class S, int LAYOUT, bool DAG, bool DPP16, bool MINV, bool CHI>
 __global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(WavesPerEU<S>::v, WavesPerEU<S>::v))) hop_kernel(HopK k) {
+__attribute__((amdgpu_waves_per_eu(WavesPerEU<S, LAYOUT, DPP16>::v, WavesPerEU<S, LAYOUT, DPP16>::v)))
+hop_kernel(HopK k) {
   extern __shared__ __align__(16) unsigned char smem[];
   // the XCD remap hands each XCD a contiguous range of logical blocks
   const int L = k.xcd ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;

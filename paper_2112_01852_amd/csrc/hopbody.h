@@ -46,8 +46,14 @@ struct HopK {
 
 // Target occupancy (waves per SIMD) the register allocator plans for: two for
 // 32- and 64-bit storage, whose arithmetic needs the registers to keep two
-// directions' neighbour loads in flight, three for 16-bit storage.
-template <class S> struct WavesPerEU { static constexpr int v = sizeof(S) >= 4 ? 2 : 3; };
+// directions' neighbour loads in flight; four for the packed FP16 path
+// (interleaved layout, Ls = 16: neighbour spinors stay packed, 105-114
+// registers, no spills), three for other 16-bit storage (which spills at
+// four).
+template <class S, int LAYOUT = QDWF_RRII, bool DPP16 = false> struct WavesPerEU {
+  static constexpr int v =
+      sizeof(S) >= 4 ? 2 : (std::is_same<S, _Float16>::value && LAYOUT == QDWF_RIRI && DPP16) ? 4 : 3;
+};
 
 // One block's share of a hop launch: logical block L of the launch described
 // by k (its sites, parity and right-hand sides), with smem the block's LDS
