@@ -310,6 +310,30 @@ int qdwf_tune(qdwf_ctx* ctx, int prec, int layout, int nrhs, void* ws, void* str
 /* The shape the operators will use: {threads, nrhs per block, xcd order, lds reservation}. */
 int qdwf_tuned_shape(qdwf_ctx* ctx, int prec, int layout, int dagger, int nrhs, int32_t* shape4);
 
+/* Traversal and layout search for the lattice of `act` (Section 4.3 compares
+ * the two complex layouts; the site order is this library's own choice).
+ * The site traversal order -- the split dimension cut into 8 slabs (one per
+ * XCD), the sweep dimension, and the tile over the other dimensions -- is
+ * fixed when a context is created, and the spinor layout when a field is
+ * packed, so the search runs on throwaway contexts on `device` (unit links,
+ * zero fields): for each candidate traversal (split z / sweep t with x tiles
+ * of 32 or 16 and y tiles of 2, 4 or 8; split y / sweep t; split t / sweep z,
+ * each capped by the extents) and each layout (RIRI, RRII) it times
+ * qdwf_apply_D (dagger 0, precision prec, nrhs right-hand sides, the launch
+ * shape each context would use). choice7 receives {split, sweep, tile x,
+ * tile y, tile z, tile t, layout} of the fastest, best_ms (may be NULL) its
+ * time per application. If QDWF_TUNE_CACHE names a file the choice is
+ * appended to it, keyed by lattice, Ls and device architecture, and every
+ * later qdwf_create of that lattice and Ls takes that traversal (unless
+ * QDWF_ORDER or QDWF_TILE is set); the caller packs in the returned layout.
+ * Allocates device memory (the contexts, canonical unit links and two
+ * fields); synchronous on `stream`. */
+int qdwf_tune_traversal(const qdwf_action* act, int device, int prec, int nrhs, void* stream,
+                        int32_t* choice7, double* best_ms);
+/* The traversal of a context: {split, sweep, tile x, tile y, tile z, tile t}
+ * (host buffer of 6 int32). */
+int qdwf_traversal(qdwf_ctx* ctx, int32_t* order6);
+
 /* ---- serving pool ----------------------------------------------------- */
 /* Continuous batching of independent solves of M_pc^dag M_pc x_o = b_o, each
  * with its own lattice, action, gauge field and source. Requests wait in FIFO

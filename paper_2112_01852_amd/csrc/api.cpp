@@ -119,7 +119,25 @@ hipError_t upload_tables(qdwf_ctx* c, bool with_geom) {
   return e;
 }
 
-std::shared_ptr<const GeomTables> build_geometry(const int L[4], const int bc[4]) {
+Traversal default_traversal(const int L[4], int sd, int wd) {
+  Traversal t;
+  t.split = sd;
+  t.sweep = wd;
+  if (sd == 2 && wd == 3) {
+    t.tile[0] = std::min(L[0], 32);
+    t.tile[1] = std::min(L[1], 4);
+    t.tile[2] = std::max(1, L[2] / 8);
+    t.tile[3] = 1;
+  } else {
+    for (int mu = 0; mu < 4; ++mu) t.tile[mu] = std::min(L[mu], 4);
+    t.tile[sd] = std::max(1, L[sd] / 8);
+  }
+  t.tile[wd] = 1;
+  return t;
+}
+
+std::shared_ptr<const GeomTables> build_geometry(const int L[4], const int bc[4],
+                                                 const Traversal& tr) {
   auto G = std::make_shared<GeomTables>();
   const int V = L[0] * L[1] * L[2] * L[3], Vh = V / 2;
   for (int mu = 0; mu < 4; ++mu) { G->L[mu] = L[mu]; G->bc[mu] = bc[mu]; }
@@ -130,27 +148,9 @@ std::shared_ptr<const GeomTables> build_geometry(const int L[4], const int bc[4]
   // XCD works on at any moment then form a compact 4D region whose
   // neighbours are still in its L2, and all XCDs advance along the sweep
   // together, so neighbours shared across XCDs meet in the last-level cache.
-  // Defaults: split z, sweep t, (x, y, z) tile 32 x 4 x Lz/8. Overrides:
-  // QDWF_ORDER="split,sweep" (dimension numbers 0..3 = x, y, z, t) and
-  // QDWF_TILE="tx,ty,tz[,tt]" (the entry of the sweep dimension is ignored).
-  int sd = 2, wd = 3;
-  if (const char* e = std::getenv("QDWF_ORDER")) {
-    int a = -1, b = -1;
-    if (std::sscanf(e, "%d,%d", &a, &b) == 2 && a >= 0 && a < 4 && b >= 0 && b < 4 && a != b) {
-      sd = a; wd = b;
-    }
-  }
-  int tile[4] = {std::min(L[0], 32), std::min(L[1], 4), std::max(1, L[2] / 8), 1};
-  if (sd != 2 || wd != 3) {
-    for (int mu = 0; mu < 4; ++mu) tile[mu] = std::min(L[mu], 4);
-    tile[sd] = std::max(1, L[sd] / 8);
-  }
-  if (const char* e = std::getenv("QDWF_TILE")) {
-    int t4[4] = {0, 0, 0, 1};
-    const int n = std::sscanf(e, "%d,%d,%d,%d", &t4[0], &t4[1], &t4[2], &t4[3]);
-    if (n >= 3 && t4[0] > 0 && t4[1] > 0 && t4[2] > 0 && t4[3] > 0)
-      for (int mu = 0; mu < 4; ++mu) tile[mu] = t4[mu];
-  }
+  const int sd = tr.split, wd = tr.sweep;
+  int tile[4];
+  for (int mu = 0; mu < 4; ++mu) tile[mu] = std::max(1, tr.tile[mu]);
   tile[wd] = 1;
   for (int k = 0; k < 4; ++k) G->tile[k] = tile[k];
   G->order[0] = sd;
@@ -266,6 +266,12 @@ extern "C" {
 const char* qdwf_last_error(void) { return g_err.c_str(); }
 
 int qdwf_create(const qdwf_action* act, int device, qdwf_ctx** out) {
+  return qdwf::create_context(act, device, nullptr, out);
+}
+
+}  // extern "C"
+
+int qdwf::create_context(const qdwf_action* act, int device, const Traversal* tr, qdwf_ctx** out) {
   if (!act || !out) return fail(QDWF_EINVAL, "null argument");
   *out = nullptr;
   for (int mu = 0; mu < 4; ++mu) {
@@ -301,7 +307,7 @@ int qdwf_create(const qdwf_action* act, int device, qdwf_ctx** out) {
   g.Vh = g.V / 2;
   g.n5h = (long)g.Vh * g.Ls;
   try {
-    c->geo = build_geometry(act->L, act->bc);
+    c->geo = build_geometry(act->L, act->bc, tr ? *tr : pick_traversal(act->L, act->Ls, device));
     c->h_mat = build_local_matrices(*act);
   } catch (const std::bad_alloc&) {
     delete c;
@@ -328,6 +334,8 @@ int qdwf_create(const qdwf_action* act, int device, qdwf_ctx** out) {
   *out = c;
   return QDWF_OK;
 }
+
+extern "C" {
 
 int qdwf_destroy(qdwf_ctx* ctx) {
   if (!ctx) return QDWF_OK;

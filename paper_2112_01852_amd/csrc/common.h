@@ -136,8 +136,27 @@ struct SolveGraph {
   double delta2 = -1.0;
 };
 
+// Site traversal order of a lattice: the split dimension (cut into 8 slabs,
+// one per XCD), the sweep dimension, and the tile over the other dimensions
+// (tile[sweep] is 1).
+struct Traversal {
+  int split, sweep;
+  int tile[4];
+};
+// The default tile for a split and sweep dimension: (x, y, z) tile
+// 32 x 4 x Lz/8 for split z, sweep t; otherwise 4 on every dimension and
+// L/8 on the split one (each capped by the extent).
+Traversal default_traversal(const int L[4], int split, int sweep);
+// The traversal a new context of this lattice takes: QDWF_ORDER /
+// QDWF_TILE if either is set; else the last one qdwf_tune_traversal stored
+// in the QDWF_TUNE_CACHE file for this lattice, Ls and device architecture
+// (not looked up when Ls <= 0); else default_traversal(L, 2, 3).
+Traversal pick_traversal(const int L[4], int Ls, int device);
+// qdwf_create with the traversal tr (nullptr: pick_traversal's).
+int create_context(const qdwf_action* act, int device, const Traversal* tr, qdwf_ctx** out);
 // Builds the tables (throws std::bad_alloc on host memory exhaustion).
-std::shared_ptr<const GeomTables> build_geometry(const int L[4], const int bc[4]);
+std::shared_ptr<const GeomTables> build_geometry(const int L[4], const int bc[4],
+                                                 const Traversal& tr);
 
 // Device arrays of a context, each on a 256-byte boundary of one block:
 // byte offsets, SIZE_MAX where absent. geom_bytes: the site tables, which come

@@ -214,7 +214,9 @@ int acquire_geometry(qdwf_pool* p, const qdwf_action& a, hipStream_t st, GeoEntr
   }
   note_peak(p);
   try {
-    e.tables = build_geometry(a.L, a.bc);
+    // every Ls of a lattice shape shares its tables: the traversal is the
+    // environment's or the default, never a per-Ls tuned one
+    e.tables = build_geometry(a.L, a.bc, pick_traversal(a.L, 0, p->device));
   } catch (const std::bad_alloc&) {
     p->alloc.release(e.off, e.bytes);
     return fail(QDWF_ENOMEM, "host allocation of the site tables failed");

@@ -1,4 +1,5 @@
-// Autotuner for the hop kernel's launch shape.
+// Autotuner for the hop kernel's launch shape and for the site traversal
+// order and spinor layout.
 //
 // For a context, precision, layout and number of right-hand sides, every
 // candidate shape -- threads per block, right-hand sides per block, XCD-aware
@@ -8,11 +9,19 @@
 // results are appended there (one JSON object per line, keyed by lattice, Ls,
 // precision, layout, dagger, nrhs and device architecture) and read back when
 // a context of the same shape is created, so tuning happens once per machine.
+//
+// The traversal order (split and sweep dimension, tile) is fixed when a
+// context is created, since the links and every packed field follow it, and
+// the layout is the caller's choice when packing; qdwf_tune_traversal
+// therefore times candidates on throwaway contexts (unit links, zero fields)
+// and reports the fastest traversal and layout, which qdwf_create of the same
+// lattice then takes from the cache.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -79,7 +88,88 @@ bool cache_load(const std::string& key, HopShape* out) {
   return found;
 }
 
+std::string trav_key(const int L[4], int Ls, int device) {
+  char buf[160];
+  snprintf(buf, sizeof(buf), "trav_%dx%dx%dx%d_Ls%d_%s", L[0], L[1], L[2], L[3], Ls,
+           arch_name(device).c_str());
+  return buf;
+}
+
+void trav_store(const std::string& key, const Traversal& t, int layout, int prec, int nrhs,
+                double ms) {
+  const char* path = std::getenv("QDWF_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "{\"key\": \"%s\", \"split\": %d, \"sweep\": %d, \"tile\": [%d, %d, %d, %d], "
+               "\"layout\": %d, \"prec\": %d, \"nrhs\": %d, \"ms\": %.6f}\n",
+               key.c_str(), t.split, t.sweep, t.tile[0], t.tile[1], t.tile[2], t.tile[3], layout,
+               prec, nrhs, ms);
+  std::fclose(f);
+}
+
+bool trav_load(const std::string& key, Traversal* out) {
+  const char* path = std::getenv("QDWF_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    char k[160];
+    Traversal t;
+    if (std::sscanf(line, "{\"key\": \"%159[^\"]\", \"split\": %d, \"sweep\": %d, \"tile\": [%d, %d, %d, %d]",
+                    k, &t.split, &t.sweep, &t.tile[0], &t.tile[1], &t.tile[2], &t.tile[3]) == 7 &&
+        key == k && t.split >= 0 && t.split < 4 && t.sweep >= 0 && t.sweep < 4 &&
+        t.split != t.sweep && t.tile[0] > 0 && t.tile[1] > 0 && t.tile[2] > 0 && t.tile[3] > 0) {
+      *out = t;   // the last entry for a key wins
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+__global__ void unit_gauge_kernel(double* U, long n) {
+  // canonical complex128 links, 9 complex entries per link: the identity
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const int ab = (int)(i % 9);
+    U[2 * i] = (ab % 4 == 0) ? 1.0 : 0.0;
+    U[2 * i + 1] = 0.0;
+  }
+}
+
 }  // namespace
+
+Traversal pick_traversal(const int L[4], int Ls, int device) {
+  const char* eo = std::getenv("QDWF_ORDER");
+  const char* et = std::getenv("QDWF_TILE");
+  if ((eo && *eo) || (et && *et)) {
+    int sd = 2, wd = 3;
+    if (eo) {
+      int a = -1, b = -1;
+      if (std::sscanf(eo, "%d,%d", &a, &b) == 2 && a >= 0 && a < 4 && b >= 0 && b < 4 && a != b) {
+        sd = a;
+        wd = b;
+      }
+    }
+    Traversal t = default_traversal(L, sd, wd);
+    if (et) {
+      int t4[4] = {0, 0, 0, 1};
+      const int n = std::sscanf(et, "%d,%d,%d,%d", &t4[0], &t4[1], &t4[2], &t4[3]);
+      if (n >= 3 && t4[0] > 0 && t4[1] > 0 && t4[2] > 0 && t4[3] > 0)
+        for (int mu = 0; mu < 4; ++mu) t.tile[mu] = t4[mu];
+      t.tile[wd] = 1;
+    }
+    return t;
+  }
+  Traversal t;
+  if (Ls > 0) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (trav_load(trav_key(L, Ls, device), &t)) return t;
+  }
+  return default_traversal(L, 2, 3);
+}
 
 bool tuned_shape(const qdwf_ctx* ctx, int prec, int layout, int dagger, int nrhs, HopShape* out) {
   std::lock_guard<std::mutex> lk(g_mu);
@@ -215,6 +305,130 @@ int qdwf_tune(qdwf_ctx* ctx, int prec, int layout, int nrhs, void* ws, void* str
   forget_graph(ctx);   // a solve's cached iterations used the previous shapes
   set_error("");
   if (prev >= 0) (void)hipSetDevice(prev);
+  return QDWF_OK;
+}
+
+int qdwf_tune_traversal(const qdwf_action* act, int device, int prec, int nrhs, void* stream,
+                        int32_t* choice7, double* best_ms) {
+  if (!act || !choice7) return fail(QDWF_EINVAL, "null argument");
+  if (prec < QDWF_F64 || prec > QDWF_BF16) return fail(QDWF_EINVAL, "unknown precision %d", prec);
+  if (nrhs < 1 || nrhs > 4096) return fail(QDWF_EINVAL, "nrhs out of range");
+  int prev = -1;
+  (void)hipGetDevice(&prev);
+  struct Restore {
+    int d;
+    ~Restore() { if (d >= 0) (void)hipSetDevice(d); }
+  } restore{prev};
+  // candidates: split z, sweep t with (x, y) tiles of 32 or 16 by 2, 4 or 8
+  // (z tile Lz/8), and the default tiles of split y / sweep t and split t /
+  // sweep z; duplicates after capping by the extents are dropped
+  const int* L = act->L;
+  std::vector<Traversal> cands;
+  auto add = [&](Traversal t) {
+    for (int mu = 0; mu < 4; ++mu) t.tile[mu] = std::max(1, std::min(t.tile[mu], L[mu]));
+    t.tile[t.sweep] = 1;
+    for (const Traversal& u : cands)
+      if (u.split == t.split && u.sweep == t.sweep && std::equal(u.tile, u.tile + 4, t.tile)) return;
+    cands.push_back(t);
+  };
+  add(default_traversal(L, 2, 3));
+  for (int tx : {32, 16})
+    for (int ty : {4, 2, 8}) {
+      Traversal t = default_traversal(L, 2, 3);
+      t.tile[0] = tx;
+      t.tile[1] = ty;
+      add(t);
+    }
+  add(default_traversal(L, 1, 3));
+  add(default_traversal(L, 3, 2));
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int reps = 5;
+  double best_t = 1e30;
+  Traversal best = cands[0];
+  int best_layout = QDWF_RIRI;
+  void* dU = nullptr;
+  void* dbuf = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = QDWF_OK;
+  for (const Traversal& t : cands) {
+    qdwf_ctx* c = nullptr;
+    rc = create_context(act, device, &t, &c);
+    if (rc) break;
+    if (!dU) {
+      // unit links (the timing does not depend on their values) and two
+      // zero fields, allocated once on this device
+      const long nlink = 4L * c->g.V * 9;
+      const size_t field = (size_t)2 * c->g.n5h * 24 * nrhs * prec_bytes(prec);
+      const size_t fal = (field + 255) & ~(size_t)255;
+      hipError_t e = hipMalloc(&dU, (size_t)nlink * 16);
+      if (e == hipSuccess) e = hipMalloc(&dbuf, 2 * fal);
+      if (e == hipSuccess) e = hipMemsetAsync(dbuf, 0, 2 * fal, st);
+      if (e == hipSuccess) {
+        hipLaunchKernelGGL(unit_gauge_kernel, dim3(1024), dim3(256), 0, st,
+                           reinterpret_cast<double*>(dU), nlink);
+        e = hipGetLastError();
+      }
+      if (e == hipSuccess) e = hipEventCreate(&e0);
+      if (e == hipSuccess) e = hipEventCreate(&e1);
+      if (e != hipSuccess) {
+        qdwf_destroy(c);
+        rc = fail(e == hipErrorOutOfMemory ? QDWF_ENOMEM : QDWF_EDEVICE,
+                  "traversal tuning buffers: %s", hipGetErrorString(e));
+        break;
+      }
+    }
+    rc = qdwf_set_gauge(c, dU, QDWF_F64, stream);
+    if (rc) {
+      qdwf_destroy(c);
+      break;
+    }
+    const size_t field = (size_t)2 * c->g.n5h * 24 * nrhs * prec_bytes(prec);
+    char* in = reinterpret_cast<char*>(dbuf);
+    char* out = in + ((field + 255) & ~(size_t)255);
+    for (int layout : {QDWF_RIRI, QDWF_RRII}) {
+      rc = qdwf_apply_D(c, out, in, 0, prec, layout, nrhs, stream);   // warm-up
+      if (rc) break;
+      hipError_t e = hipEventRecord(e0, st);
+      for (int r = 0; r < reps && e == hipSuccess && rc == QDWF_OK; ++r)
+        rc = qdwf_apply_D(c, out, in, 0, prec, layout, nrhs, stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) rc = fail(QDWF_EDEVICE, "traversal timing: %s", hipGetErrorString(e));
+      if (rc) break;
+      if (ms / reps < best_t) {
+        best_t = ms / reps;
+        best = t;
+        best_layout = layout;
+      }
+    }
+    qdwf_destroy(c);
+    if (rc) break;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (dbuf) (void)hipFree(dbuf);
+  if (dU) (void)hipFree(dU);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    trav_store(trav_key(L, act->Ls, device), best, best_layout, prec, nrhs, best_t);
+  }
+  choice7[0] = best.split;
+  choice7[1] = best.sweep;
+  for (int k = 0; k < 4; ++k) choice7[2 + k] = best.tile[k];
+  choice7[6] = best_layout;
+  if (best_ms) *best_ms = best_t;
+  set_error("");
+  return QDWF_OK;
+}
+
+int qdwf_traversal(qdwf_ctx* ctx, int32_t* order6) {
+  if (!ctx || !order6) return fail(QDWF_EINVAL, "null argument");
+  order6[0] = ctx->order[0];
+  order6[1] = ctx->order[1];
+  for (int k = 0; k < 4; ++k) order6[2 + k] = ctx->tile[k];
   return QDWF_OK;
 }
 

@@ -94,6 +94,8 @@ _SIG = {
     "qdwf_geometry_tables": ([_P, _P, _P, _P], _I),
     "qdwf_tune": ([_P, _I, _I, _I, _P, _P, _P], _I),
     "qdwf_tuned_shape": ([_P, _I, _I, _I, _I, _P], _I),
+    "qdwf_tune_traversal": ([ctypes.POINTER(qdwf_action), _I, _I, _I, _P, _P, _P], _I),
+    "qdwf_traversal": ([_P, _P], _I),
     "qdwf_request_bytes": ([ctypes.POINTER(qdwf_action), ctypes.POINTER(qdwf_solve_params)],
                            ctypes.c_size_t),
     "qdwf_pool_overhead_bytes": ([_I], ctypes.c_size_t),
@@ -324,6 +326,24 @@ def qdwf_tuned_shape(ctx, prec, layout, dagger, nrhs):
     _check(lib().qdwf_tuned_shape(ctx, int(prec), int(layout), int(dagger), int(nrhs),
                                   ctypes.cast(out, ctypes.c_void_p)))
     return dict(threads=out[0], nrb=out[1], xcd=out[2], lds_pad=out[3])
+
+
+def qdwf_tune_traversal(act: qdwf_action, device, prec, nrhs, stream=None):
+    """Searches site traversal orders and layouts on throwaway contexts;
+    returns (dict(split, sweep, tile, layout), best ms)."""
+    out = (ctypes.c_int32 * 7)()
+    best = ctypes.c_double(0.0)
+    _check(lib().qdwf_tune_traversal(ctypes.byref(act), int(device), int(prec), int(nrhs),
+                                     _stream(stream), ctypes.cast(out, ctypes.c_void_p),
+                                     ctypes.cast(ctypes.byref(best), ctypes.c_void_p)))
+    return dict(split=out[0], sweep=out[1], tile=tuple(out[2:6]), layout=out[6]), best.value
+
+
+def qdwf_traversal(ctx):
+    """{split, sweep, tile} of a context's site traversal order."""
+    out = (ctypes.c_int32 * 6)()
+    _check(lib().qdwf_traversal(ctx, ctypes.cast(out, ctypes.c_void_p)))
+    return dict(split=out[0], sweep=out[1], tile=tuple(out[2:6]))
 
 
 def qdwf_request_bytes(act: qdwf_action, params: qdwf_solve_params) -> int:
