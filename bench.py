@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 # (profiles/sweep_f32_riri_32x32x32x32x16.md),
 # keyed by the hash of the kernel source they were taken with; any other
 # source reports null until it is profiled again.
-MEASURED_TRAFFIC = {"e7ae42295e6ecee1": 6.5723e9}
+MEASURED_TRAFFIC = {"078bda3b3d513dfb": 6.5771e9}
 FLOPS_PER_SITE = 1320        # Table 3 (real flops per 5D site per hop)
 MOBIUS = dict(M5=1.8, mf=0.01, b=1.5, c=0.5)
 
@@ -371,8 +371,10 @@ def solver_bench(args, torch, q, I):
 
 def multi_rhs_bench(args, torch, q, I):
     """24 right-hand sides at 16^4 x 16 (12 point sources, one per spin and
-    colour at the origin, plus 12 Gaussian): batched eo hop and batched
-    mixed-precision solve of D x = b, against plain FP64 solves one at a time."""
+    colour at the origin, plus 12 Gaussian): the batched eo hop against one
+    right-hand side, and the solve of D x = b for all 24 four ways: batched
+    mixed precision (FP32 inner), batched plain FP64, and each source on its
+    own in mixed precision and in plain FP64 (all 24 timed)."""
     L, Ls, nrhs = (16, 16, 16, 16), 16, 24
     U = I.gauge_field(L, "haar", 4000)
     srcs = [I.point_source(L, Ls, sp, c) for sp in range(4) for c in range(3)]
@@ -398,35 +400,46 @@ def multi_rhs_bench(args, torch, q, I):
     log("multi-rhs hop", out)
     del fin, fout, f1, o1
     bf = D.pack(b, q.QDWF_F64, q.QDWF_RIRI, q.QDWF_FULL, nrhs)
-    x = D.field(q.QDWF_F64, q.QDWF_FULL, nrhs)
-    ws = D.workspace(q.QDWF_OP_SOLVE, q.QDWF_F32, nrhs)
-    prm = q.solve_params(system=q.QDWF_SYS_FULL, inner_prec=q.QDWF_F32, tol=1e-10,
-                         check_every=8, use_graph=1)
-    torch.cuda.synchronize()
-    t0 = time.time()
-    rc, st = q.qdwf_solve(D.ctx, x, bf, nrhs, prm, ws)
-    dt = time.time() - t0
-    out["solve_batched_mixed_f32"] = {"rc": rc, "seconds": dt, "solves_per_s": nrhs / dt,
-                                      "iterations": st.iterations,
-                                      "full_residual": st.full_residual,
-                                      "converged": st.converged}
-    log("multi-rhs solve", out["solve_batched_mixed_f32"])
-    del x, ws, bf
-    torch.cuda.empty_cache()
-    # plain FP64 CG one source at a time (a sample of 3; solves/s extrapolates linearly)
-    ws = D.workspace(q.QDWF_OP_SOLVE, q.QDWF_F64, 1)
-    prm = q.solve_params(system=q.QDWF_SYS_FULL, inner_prec=q.QDWF_F64, tol=1e-10,
-                         check_every=8, use_graph=1)
-    times = []
-    for j in (0, 5, 12):
-        bj = D.pack(b[j], q.QDWF_F64, q.QDWF_RIRI, q.QDWF_FULL, 1)
-        xj = D.field(q.QDWF_F64, q.QDWF_FULL, 1)
+
+    def batched(inner):
+        x = D.field(q.QDWF_F64, q.QDWF_FULL, nrhs)
+        ws = D.workspace(q.QDWF_OP_SOLVE, inner, nrhs)
+        prm = q.solve_params(system=q.QDWF_SYS_FULL, inner_prec=inner, tol=1e-10,
+                             check_every=8, use_graph=1)
         torch.cuda.synchronize()
         t0 = time.time()
-        rc1, st1 = q.qdwf_solve(D.ctx, xj, bj, 1, prm, ws)
-        times.append(time.time() - t0)
-    out["solve_sequential_f64"] = {"sampled_sources": 3, "mean_seconds": float(np.mean(times)),
-                                   "solves_per_s": 1.0 / float(np.mean(times))}
+        rc, st = q.qdwf_solve(D.ctx, x, bf, nrhs, prm, ws)
+        dt = time.time() - t0
+        del x, ws
+        torch.cuda.empty_cache()
+        return {"rc": rc, "seconds": dt, "solves_per_s": nrhs / dt, "iterations": st.iterations,
+                "full_residual": st.full_residual, "converged": st.converged}
+
+    def sequential(inner):
+        # every one of the 24 sources solved on its own, one after another
+        ws = D.workspace(q.QDWF_OP_SOLVE, inner, 1)
+        prm = q.solve_params(system=q.QDWF_SYS_FULL, inner_prec=inner, tol=1e-10,
+                             check_every=8, use_graph=1)
+        times, worst = [], 0.0
+        for j in range(nrhs):
+            bj = D.pack(b[j], q.QDWF_F64, q.QDWF_RIRI, q.QDWF_FULL, 1)
+            xj = D.field(q.QDWF_F64, q.QDWF_FULL, 1)
+            torch.cuda.synchronize()
+            t0 = time.time()
+            rc1, st1 = q.qdwf_solve(D.ctx, xj, bj, 1, prm, ws)
+            times.append(time.time() - t0)
+            worst = max(worst, st1.full_residual)
+        del ws
+        return {"sources": nrhs, "total_seconds": float(np.sum(times)),
+                "solves_per_s": nrhs / float(np.sum(times)), "worst_full_residual": worst}
+
+    out["solve_batched_mixed_f32"] = batched(q.QDWF_F32)
+    log("multi-rhs solve batched mixed", out["solve_batched_mixed_f32"])
+    out["solve_batched_f64"] = batched(q.QDWF_F64)
+    log("multi-rhs solve batched fp64", out["solve_batched_f64"])
+    out["solve_sequential_mixed_f32"] = sequential(q.QDWF_F32)
+    log("sequential mixed", out["solve_sequential_mixed_f32"])
+    out["solve_sequential_f64"] = sequential(q.QDWF_F64)
     log("sequential fp64", out["solve_sequential_f64"])
     D.close()
     return out
@@ -609,7 +622,7 @@ def main():
                     default=[0.5, 0.9, 1.2],
                     help="offered loads relative to the mixed pool's saturation throughput")
     ap.add_argument("--serve-budget-gb", type=float, default=48.0)
-    ap.add_argument("--only", choices=["solver", "wilson", "serving"], default=None,
+    ap.add_argument("--only", choices=["solver", "wilson", "serving", "multi"], default=None,
                     help="run only this row and print its JSON object (for profiling)")
     ap.add_argument("--inner", default="",
                     help="comma list of solver inner precisions (f64,f32,f16,bf16; default all)")
@@ -632,6 +645,10 @@ def main():
     if args.only == "serving":
         print(json.dumps({"serving": serving_bench(args, torch, q)}), flush=True)
         return
+    if args.only == "multi":
+        print(json.dumps({"multi_rhs_16x16x16x16x16_n24": multi_rhs_bench(args, torch, q, I)}),
+              flush=True)
+        return
     if args.only == "wilson":
         probe = copy_probe(torch)   # also the counters' calibration copy
         print(json.dumps({"attainable_hbm": probe,
@@ -641,6 +658,10 @@ def main():
     log("copy probe", probe)
     dres, sites = dslash_bench(args, torch, q, I)
     cands = [k for k in ("D_f32_riri", "D_f32_rrii") if k in dres]
+    if not cands:
+        # --variants without an FP32 one: no headline, only the rows timed
+        print(json.dumps({"dslash": dres}), flush=True)
+        return
     best = min(cands, key=lambda k: dres[k]["ms"])
     best_layout = best.split("_")[-1]
     head = dres[best]
