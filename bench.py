@@ -524,7 +524,7 @@ def cpu_baseline(fp64_cg_iterations=None, min_seconds=10.0, max_reps=4):
       * D at 16^4 x 16 Mobius, 1 thread (32^4 x 16 at one thread would take
         a minute; the per-site rate is what is compared);
       * the normal-equation CG at 24^4 x 16 (smoothed links, mf 0.01), all
-        cores: time per iteration from 3 iterations (each iteration, and the
+        cores: time per iteration from 1 iteration (each iteration, and the
         closing residual, is one M_pc^dag M_pc), extrapolated to the
         iteration count of the FP64 solve on the GPU (labelled as such).
     `value` is the first leg, in the headline's unit (GFlop/s, 1320 flops per
@@ -578,7 +578,7 @@ def cpu_baseline(fp64_cg_iterations=None, min_seconds=10.0, max_reps=4):
     a = cpu.Action(L=L, Ls=Ls, **MOBIUS)
     U = I.gauge_field(L, "smooth", 3000, eps=0.3)
     b = cpu.restrict(I.gaussian_spinor(L, Ls, 3001), L, 1)
-    k = 3
+    k = 1
     t0 = time.time()
     x, it, res = cpu.cg(a, U, b, tol=1e-10, max_iter=k)
     dt = time.time() - t0

@@ -327,7 +327,8 @@ int qdwf_tuned_shape(qdwf_ctx* ctx, int prec, int layout, int dagger, int nrhs, 
  * later qdwf_create of that lattice and Ls takes that traversal (unless
  * QDWF_ORDER or QDWF_TILE is set); the caller packs in the returned layout.
  * Allocates device memory (the contexts, canonical unit links and two
- * fields); synchronous on `stream`. */
+ * fields) on `device`; `stream` must belong to `device`; synchronous.
+ * Returns QDWF_EINVAL for an invalid action, device or precision. */
 int qdwf_tune_traversal(const qdwf_action* act, int device, int prec, int nrhs, void* stream,
                         int32_t* choice7, double* best_ms);
 /* The traversal of a context: {split, sweep, tile x, tile y, tile z, tile t}

@@ -313,12 +313,17 @@ int qdwf_tune_traversal(const qdwf_action* act, int device, int prec, int nrhs, 
   if (!act || !choice7) return fail(QDWF_EINVAL, "null argument");
   if (prec < QDWF_F64 || prec > QDWF_BF16) return fail(QDWF_EINVAL, "unknown precision %d", prec);
   if (nrhs < 1 || nrhs > 4096) return fail(QDWF_EINVAL, "nrhs out of range");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(QDWF_EINVAL, "device %d not available (%d devices)", device, ndev);
   int prev = -1;
   (void)hipGetDevice(&prev);
   struct Restore {
     int d;
     ~Restore() { if (d >= 0) (void)hipSetDevice(d); }
   } restore{prev};
+  // the buffers and launches below belong to `device`
+  if (hipSetDevice(device) != hipSuccess) return fail(QDWF_EDEVICE, "hipSetDevice(%d) failed", device);
   // candidates: split z, sweep t with (x, y) tiles of 32 or 16 by 2, 4 or 8
   // (z tile Lz/8), and the default tiles of split y / sweep t and split t /
   // sweep z; duplicates after capping by the extents are dropped
