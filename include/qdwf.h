@@ -177,11 +177,11 @@ int qdwf_unpack_spinor(qdwf_ctx* ctx, void* dst, int dst_prec, const void* src, 
 /* ---- operators (all asynchronous on `stream`; out must not alias in) --- */
 /* Full 5D domain-wall operator: out = D in (dagger = 0) or D^dag in
  * (dagger = 1). in, out: full fields, nrhs right-hand sides. With Ls = 16,
- * the interleaved layout and FP32 storage with 16- or 32-wide x rows, or FP16
- * storage with 32-wide rows, it runs as a sweep of whole x-rows along t (same
- * result up to FP32 rounding order); the environment variable QDWF_SWEEP=1 / 0
- * forces that form on (also for BF16 storage and other row widths in
- * {8, 16, 24, 32}) or off. */
+ * the interleaved layout and FP32 storage with 16- or 32-wide x rows, it
+ * runs as a sweep of whole x-rows along t (same result up to FP32 rounding
+ * order); the environment variable QDWF_SWEEP=1 / 0 forces that form on
+ * (also for FP16 and BF16 storage and other row widths in {8, 16, 24, 32})
+ * or off. */
 int qdwf_apply_D(qdwf_ctx* ctx, void* out, const void* in, int dagger, int prec, int layout,
                  int nrhs, void* stream);
 

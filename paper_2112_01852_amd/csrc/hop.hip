@@ -70,11 +70,12 @@ HopShape default_shape(const qdwf_ctx* ctx, int prec, int nrhs) {
   sh.lds_pad = 0;
   // the t-sweep of the full operator: measured faster than the checkerboard
   // traversal in FP32 with 16- and 32-wide rows (one and two blocks of 8
-  // waves per CU) and in FP16 storage with 32-wide rows; slower with 24-wide
-  // ones (6 waves per CU), FP16 in 16-wide rows and BF16 storage; the tuner
-  // tries it wherever it applies
+  // waves per CU); slower with 24-wide ones (6 waves per CU), in BF16
+  // storage, and in FP16 storage since the checkerboard kernel keeps FP16
+  // neighbours packed (32^4 x 16 D 0.76 against 0.84 ms); the tuner tries
+  // it wherever it applies
   const int Lx = ctx->g.L[0];
-  sh.sweep = ((prec == QDWF_F32 && (Lx == 16 || Lx == 32)) || (prec == QDWF_F16 && Lx == 32)) ? 1 : 0;
+  sh.sweep = (prec == QDWF_F32 && (Lx == 16 || Lx == 32)) ? 1 : 0;
   if (const char* e = std::getenv("QDWF_HOP_LDS_PAD")) sh.lds_pad = std::atoi(e);
   if (const char* e = std::getenv("QDWF_HOP_THREADS")) {
     const int t = std::atoi(e);

@@ -77,13 +77,13 @@ def _rel_dev(torch, got, ref):
     (1, 1, 0, "0"), (1, 1, 1, "0"),        # FP32 RIRI: checkerboard kernel
     (1, 0, 0, ""), (1, 0, 1, ""),          # FP32 RRII
     (0, 1, 0, ""), (0, 1, 1, ""),          # FP64
-    (2, 1, 0, ""), (2, 1, 1, ""),          # FP16 storage (t-sweep)
-    (2, 1, 0, "0"),                        # FP16 storage, checkerboard kernel
+    (2, 1, 0, ""), (2, 1, 1, ""),          # FP16 storage (packed checkerboard kernel)
+    (2, 1, 0, "1"), (2, 1, 1, "1"),        # FP16 storage, t-sweep forced
     (3, 1, 0, ""), (3, 1, 1, ""),          # BF16 storage
 ])
 def test_D_whole_field(full, prec, layout, dagger, form, monkeypatch):
     """form: "" the library's default launch (what the benchmark times), "0"
-    the checkerboard kernel forced."""
+    the checkerboard kernel forced, "1" the t-sweep forced."""
     q, torch = full[0], full[1]
     D, psi_d = full[6], full[5]
     if form:
