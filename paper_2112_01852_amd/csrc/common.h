@@ -242,6 +242,13 @@ struct HopArgs {
               // takes as it is; with minv, the result is multiplied by A/b
   double hop_scale, alpha, beta;
   const void* links;   // links to use instead of the context's (nullptr: the context's)
+  // nullptr, or one int per right-hand side (at skip[r * skip_stride]): a
+  // block whose right-hand sides all hold a nonzero value there does no work
+  // and leaves its outputs as they were (the solver passes its per-rhs
+  // status, so the hops of a right-hand side that waits for its reliable
+  // update cost a launch, not a pass over memory)
+  const int* skip;
+  int skip_stride;
 };
 int launch_hop(qdwf_ctx* ctx, int prec, int layout, int dagger, const HopArgs& a,
                hipStream_t st, const HopShape* shape = nullptr);

@@ -42,6 +42,8 @@ struct HopK {
   int epi, xcd, minv;
   double c_over_b, mf, hop_scale_b, alpha, beta;
   double rpow[4];      // (-beta/alpha)^(2^j), j < 4: the M_ee^-1 scan
+  const int* skip;     // per-rhs skip flags (HopArgs::skip), or nullptr
+  int skip_stride;
 };
 
 // Target occupancy (waves per SIMD) the register allocator plans for: two for
@@ -86,6 +88,16 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
   const int q = 1 - p;
   const int cb0 = sb * k.nsb;
   const int Vh = k.Vh;
+  if (k.skip) {
+    // the whole block returns (before any barrier) when none of its
+    // right-hand sides is running
+    bool run = false;
+    for (int j = 0; j < k.nrb; ++j) {
+      const int r = rb * k.nrb + j;
+      if (r < k.nrhs && k.skip[(long)r * k.skip_stride] == 0) run = true;
+    }
+    if (!run) return;
+  }
 
   // Stage the neighbour indices of the block's sites (one load per thread),
   // then start this lane's first two neighbour-spinor loads, then stage the
@@ -351,6 +363,8 @@ int make_hopk(const qdwf_ctx* ctx, int prec, const HopArgs& a, const HopShape& s
   k->mf = ctx->act.mf;
   k->hop_scale_b = a.hop_scale * ctx->act.b;
   k->alpha = a.alpha; k->beta = a.beta;
+  k->skip = a.skip;
+  k->skip_stride = a.skip_stride;
   k->minv = MINV;
   if (MINV) {
     if (a.epi) return fail(QDWF_EINVAL, "fused M_ee^-1 takes no epilogue term");

@@ -41,13 +41,16 @@ struct Layout {
 Layout solver_layout(long n, int nrhs, int inner);
 
 int reduce_blocks(long n);
+// skip, skip_stride: per right-hand-side flags of the hops (HopArgs::skip)
 int apply_hop_parity(qdwf_ctx* ctx, int prec, int layout, int dagger, int out_par, void* out,
                      const void* in, const void* z, double scale, int nrhs, long rs,
-                     hipStream_t st);
+                     hipStream_t st, const int* skip = nullptr, int skip_stride = 0);
 int apply_mpc(qdwf_ctx* ctx, int prec, int layout, int dagger, void* out, const void* in,
-              void* te1, void* te2, int nrhs, long rs, hipStream_t st);
+              void* te1, void* te2, int nrhs, long rs, hipStream_t st,
+              const int* skip = nullptr, int skip_stride = 0);
 int apply_mdagm(qdwf_ctx* ctx, int prec, int layout, void* out, const void* in, void* v,
-                void* te1, void* te2, int nrhs, long rs, hipStream_t st);
+                void* te1, void* te2, int nrhs, long rs, hipStream_t st,
+                const int* skip = nullptr, int skip_stride = 0);
 int dot_re_im(qdwf_ctx* ctx, double* out_host, const void* x, const void* y, long n, int prec,
               int layout, int nrhs, void* ws, hipStream_t st);
 size_t dot_ws_bytes(long n, int nrhs);

@@ -23,6 +23,8 @@
 #include <cmath>
 #include <initializer_list>
 
+#include <cstddef>
+
 #include "cgbody.h"
 
 namespace qdwf {
@@ -37,6 +39,21 @@ __global__ void __launch_bounds__(RT) k_dot(const SA* __restrict__ a, const SB* 
                                             int vec) {
   __shared__ double sh[RT];
   k_dot_body<SA, SB>(a, b, n, rsa, rsb, part, vec, blockIdx.x, gridDim.x, blockIdx.y, sh);
+}
+
+// <p, Ap> of the iteration: right-hand sides that are not running (waiting
+// for their reliable update, or finished) contribute a zero partial, which
+// k_alpha does not read
+template <class S>
+__global__ void __launch_bounds__(RT) k_dot_pap(const S* __restrict__ a, const S* __restrict__ b,
+                                                long n, double* __restrict__ part, int vec,
+                                                const RhsState* __restrict__ st) {
+  __shared__ double sh[RT];
+  if (st[blockIdx.y].status != ST_RUN) {
+    if (threadIdx.x == 0) part[(long)blockIdx.y * gridDim.x + blockIdx.x] = 0.0;
+    return;
+  }
+  k_dot_body<S, S>(a, b, n, n, n, part, vec, blockIdx.x, gridDim.x, blockIdx.y, sh);
 }
 
 __global__ void __launch_bounds__(RT) k_alpha(const double* __restrict__ part, int NB,
@@ -171,8 +188,10 @@ int reduce_blocks(long n) {
 // ---- operator compositions ---------------------------------------------------
 int apply_hop_parity(qdwf_ctx* ctx, int prec, int layout, int dagger, int out_par, void* out,
                      const void* in, const void* z, double scale, int nrhs, long rs,
-                     hipStream_t st) {
+                     hipStream_t st, const int* skip, int skip_stride) {
   HopArgs a = {};
+  a.skip = skip;
+  a.skip_stride = skip_stride;
   a.in[out_par] = in;
   a.out[out_par] = out;
   a.z[out_par] = z;
@@ -195,7 +214,8 @@ int apply_hop_parity(qdwf_ctx* ctx, int prec, int layout, int dagger, int out_pa
 // its input as it is instead of applying A to each of its 8 neighbours;
 // M_pc^dag applies A^dag once per site inside its hops anyway.
 int apply_mpc(qdwf_ctx* ctx, int prec, int layout, int dagger, void* out, const void* in,
-              void* te1, void* te2, int nrhs, long rs, hipStream_t st) {
+              void* te1, void* te2, int nrhs, long rs, hipStream_t st, const int* skip,
+              int skip_stride) {
   int rc;
   const int chi = dagger ? 0 : 1;
   if (ctx->g.Ls == 16) {
@@ -212,11 +232,13 @@ int apply_mpc(qdwf_ctx* ctx, int prec, int layout, int dagger, void* out, const 
     a.hop_scale = -0.5;
     a.minv = 1;
     a.chi = chi;
+    a.skip = skip;
+    a.skip_stride = skip_stride;
     if ((rc = launch_hop(ctx, prec, layout, dagger, a, st))) return rc;
   } else {
     // te1 = M_eo in  (or (M_oe)^dag in), then te2 = (A/b) M_ee^-1 te1 (or M_ee^-dag te1)
     if ((rc = apply_hop_parity(ctx, prec, layout, dagger, QDWF_EVEN, te1, in, nullptr, -0.5, nrhs,
-                               rs, st)))
+                               rs, st, skip, skip_stride)))
       return rc;
     if ((rc = launch_local(ctx, prec, layout, dagger ? MAT_MEEINV_DAG : MAT_AMEEINV, te2, te1, 1, 0,
                            rs, nrhs, st)))
@@ -237,14 +259,18 @@ int apply_mpc(qdwf_ctx* ctx, int prec, int layout, int dagger, void* out, const 
   a.alpha = ctx->act.b * (4.0 - ctx->act.M5) + 1.0;
   a.beta = ctx->act.c * (4.0 - ctx->act.M5) - 1.0;
   a.chi = chi;
+  a.skip = skip;
+  a.skip_stride = skip_stride;
   return launch_hop(ctx, prec, layout, dagger, a, st);
 }
 
 int apply_mdagm(qdwf_ctx* ctx, int prec, int layout, void* out, const void* in, void* v,
-                void* te1, void* te2, int nrhs, long rs, hipStream_t st) {
+                void* te1, void* te2, int nrhs, long rs, hipStream_t st, const int* skip,
+                int skip_stride) {
   int rc;
-  if ((rc = apply_mpc(ctx, prec, layout, 0, v, in, te1, te2, nrhs, rs, st))) return rc;
-  return apply_mpc(ctx, prec, layout, 1, out, v, te1, te2, nrhs, rs, st);
+  if ((rc = apply_mpc(ctx, prec, layout, 0, v, in, te1, te2, nrhs, rs, st, skip, skip_stride)))
+    return rc;
+  return apply_mpc(ctx, prec, layout, 1, out, v, te1, te2, nrhs, rs, st, skip, skip_stride);
 }
 
 int dot_re_im(qdwf_ctx* ctx, double* out_host, const void* x, const void* y, long n, int prec,
@@ -359,10 +385,14 @@ struct Cg {
     // the workspace arrays start on 256-byte boundaries and n is a multiple of 24
     const int vec_s = vec_ok<S>(n, {p, Ap}) ? 1 : 0;
     const int vec_r = vec_ok<R>(n, {at<R>(L.off_xl), at<R>(L.off_rl)}) ? 1 : 0;
+    // the hops and p.Ap of a right-hand side that is not running do no work
+    static_assert(sizeof(RhsState) % sizeof(int) == 0, "RhsState is read as ints");
+    const int* skip = reinterpret_cast<const int*>(
+        reinterpret_cast<const char*>(d_state) + offsetof(RhsState, status));
     if ((rc = apply_mdagm(ctx, inner, layout, Ap, p, at<S>(L.off_v), at<S>(L.off_t1),
-                          at<S>(L.off_t2), nrhs, n, st)))
+                          at<S>(L.off_t2), nrhs, n, st, skip, (int)(sizeof(RhsState) / sizeof(int)))))
       return rc;
-    hipLaunchKernelGGL((k_dot<S, S>), grid(), dim3(RT), 0, st, p, Ap, n, n, n, part(), vec_s);
+    hipLaunchKernelGGL((k_dot_pap<S>), grid(), dim3(RT), 0, st, p, Ap, n, part(), vec_s, d_state);
     hipLaunchKernelGGL(k_alpha, dim3(nrhs), dim3(RT), 0, st, part(), NB, d_state);
     hipLaunchKernelGGL((k_update_xr<R, R, S>), grid(), dim3(RT), 0, st, at<R>(L.off_xl),
                        at<R>(L.off_rl), p, Ap, n, n, d_state, part(), vec_s && vec_r);

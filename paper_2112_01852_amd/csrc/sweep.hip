@@ -429,7 +429,8 @@ bool sweep_eligible(const qdwf_ctx* ctx, int prec, int layout, const HopArgs& a)
   if (!sweep_geometry(ctx->g) || layout != QDWF_RIRI) return false;
   if (prec != QDWF_F32 && prec != QDWF_F16 && prec != QDWF_BF16) return false;
   if (!ctx->d_dlinks[prec]) return false;
-  if (a.npar != 2 || a.par0 != 0 || !a.epi || a.minv || a.links || a.hop_scale == 0.0) return false;
+  if (a.npar != 2 || a.par0 != 0 || !a.epi || a.minv || a.links || a.skip || a.hop_scale == 0.0)
+    return false;
   // one full field: in[p] is the other parity's half, z[p] this parity's
   const long half = ctx->g.n5h * 24;
   const size_t hb = (size_t)half * prec_bytes(prec);
