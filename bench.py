@@ -453,7 +453,8 @@ def serving_bench(args, torch, q):
     throughput), then Poisson arrivals at rho = 0.5, 0.9 and 1.2 of that
     throughput. Baseline at every load: the same stream served first in,
     first out by plain FP64 CG one request at a time (the same pool with one
-    slot and FP64 inner precision), a real run on the same GPU."""
+    slot and FP64 inner precision), a real run on the same GPU; and, at
+    saturation, the grouped pool itself solving in plain FP64."""
     from paper_2112_01852_amd import serve
     n = args.serve_requests
     specs = serve.make_specs(n, 5000)
@@ -480,6 +481,11 @@ def serving_bench(args, torch, q):
            "mixed_inner": "f16", "check_every": 8,
            "saturation_mixed": summary(sat)}
     log("serving saturation", out["saturation_mixed"])
+    # the same pool (grouped launches, 64 slots) solving in plain FP64: what
+    # batching gives without the lower precision
+    sat64 = serve.run_pool(prepared, np.zeros(n), prm_plain, arena, slots, keep_x=False)
+    out["saturation_plain_fp64_grouped"] = summary(sat64)
+    log("serving saturation fp64 grouped", out["saturation_plain_fp64_grouped"])
     loads = {}
     for rho in args.serve_loads:
         arr = serve.poisson_arrivals(n, rho * rate, 5001)
