@@ -637,7 +637,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "(sharding across GPUs is described, not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2112_01852_amd import qdwf as q
