@@ -201,6 +201,7 @@ __device__ inline void k_beta_body(const double* __restrict__ part, int NB,
   const double rr_new = part_sum(part, NB, q, sh);
   if (threadIdx.x) return;
   RhsState& s = st[q];
+  s.xstep = s.status == ST_RUN;
   if (s.status != ST_RUN) return;
   s.iters += 1;
   if (!isfinite(rr_new)) {
@@ -248,6 +249,62 @@ __device__ inline void k_update_p_body(const SR* __restrict__ r, SP* __restrict_
   }
   for (long i = TILE * nt + (long)bx * RT + threadIdx.x; i < n; i += (long)NB * RT)
     pr[i] = Store<SP>::from((T)Store<SR>::to(rr[i]) + be * (T)Store<SP>::to(pr[i]));
+}
+
+// The vector step of the fused iteration, after r and |r|^2 came from the
+// last hop: x += alpha p (if the rhs took this iteration's step) and, while
+// it keeps running, p = r + beta p.
+template <class SX, class SR, class SP>
+__device__ inline void k_update_px_body(SX* __restrict__ x, const SR* __restrict__ r,
+                                        SP* __restrict__ p, long n, long rs,
+                                        const RhsState* __restrict__ st, int vec,
+    int bx, int NB, int q) {
+  typedef typename Store<SR>::compute T;
+  const RhsState& s = st[q];
+  if (!s.xstep) return;
+  const bool run = s.status == ST_RUN;
+  const T al = (T)s.alpha, be = (T)s.beta;
+  SX* xr = x + (long)q * rs;
+  const SR* rr = r + (long)q * rs;
+  SP* pr = p + (long)q * rs;
+  constexpr int E = ChunkWidth<SX, SR, SP>::e;
+  const long nt = vec ? n / TILE : 0;
+  const int lane = threadIdx.x & 63;
+  const long t1 = nt * (bx + 1) / NB;   // this block's contiguous range of tiles
+  for (long t = nt * bx / NB + (threadIdx.x >> 6); t < t1; t += RT / 64) {
+#pragma unroll
+    for (int j = 0; j < 8 / E; ++j) {
+      const long i = t * TILE + j * 64 * E + lane * E;
+      T pv[E], xv[E];
+      Chunk<SP, E>::ld(pr + i, pv);
+      Chunk<SX, E>::ld(xr + i, xv);
+#pragma unroll
+      for (int k = 0; k < E; ++k) xv[k] = xv[k] + al * pv[k];
+      Chunk<SX, E>::st(xr + i, xv);
+      if (run) {
+        T rv[E];
+        Chunk<SR, E>::ld(rr + i, rv);
+#pragma unroll
+        for (int k = 0; k < E; ++k) pv[k] = rv[k] + be * pv[k];
+        Chunk<SP, E>::st(pr + i, pv);
+      }
+    }
+  }
+  for (long i = TILE * nt + (long)bx * RT + threadIdx.x; i < n; i += (long)NB * RT) {
+    const T pv = (T)Store<SP>::to(pr[i]);
+    xr[i] = Store<SX>::from((T)Store<SX>::to(xr[i]) + al * pv);
+    if (run) pr[i] = Store<SP>::from((T)Store<SR>::to(rr[i]) + be * pv);
+  }
+}
+
+// part[q*NB + bx] = sum of block bx's share of the n values v[q*n ...]
+__device__ inline void k_sum_body(const double* __restrict__ v, long n, double* __restrict__ part,
+    int bx, int NB, int q, double* sh) {
+  const double* vr = v + (long)q * n;
+  double acc = 0;
+  for (long i = (long)bx * RT + threadIdx.x; i < n; i += (long)NB * RT) acc += vr[i];
+  const double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[(long)q * NB + bx] = t;
 }
 
 // ---- reliable update -------------------------------------------------------

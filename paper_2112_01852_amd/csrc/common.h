@@ -249,6 +249,20 @@ struct HopArgs {
   // update cost a launch, not a pass over memory)
   const int* skip;
   int skip_stride;
+  // CG step fused into a one-parity hop with epilogue (no minv), for the
+  // solver's M_pc p and M_pc^dag (M_pc p); cg_site[r * Vh + i] receives a
+  // sum of squares over the Ls slices of checkerboard site i of rhs r:
+  //   cg = 1: of the output as stored;
+  //   cg = 2: the output is not stored; cg_r -= alpha_r * output instead
+  //     (alpha_r = cg_alpha[r * cg_alpha_stride]; cg_r in the compute type,
+  //     double for FP64 storage and float otherwise, in the output's layout
+  //     and rhs stride), and the sums are of the updated cg_r.
+  // Rhs whose skip flag is set are left alone.
+  int cg;
+  void* cg_r;
+  const double* cg_alpha;
+  int cg_alpha_stride;
+  double* cg_site;
 };
 int launch_hop(qdwf_ctx* ctx, int prec, int layout, int dagger, const HopArgs& a,
                hipStream_t st, const HopShape* shape = nullptr);

@@ -44,6 +44,11 @@ struct HopK {
   double rpow[4];      // (-beta/alpha)^(2^j), j < 4: the M_ee^-1 scan
   const int* skip;     // per-rhs skip flags (HopArgs::skip), or nullptr
   int skip_stride;
+  int cg;              // fused CG step (HopArgs::cg)
+  void* cg_r;
+  const double* cg_alpha;
+  int cg_alpha_stride;
+  double* cg_site;
 };
 
 // Target occupancy (waves per SIMD) the register allocator plans for: two for
@@ -321,7 +326,7 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
 #pragma unroll
     for (int i = 0; i < 24; ++i) acc[i] *= hs;
   }
-  if (active) {
+  if (active && k.cg != 2) {
     S* out = reinterpret_cast<S*>(k.out[p]) + (long)rc * k.rs_out;
     if constexpr (PK) {
       long i = cbc;
@@ -333,6 +338,39 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
         pp[c * lsb] = make_uint2(pk_f16(acc[4 * c], acc[4 * c + 1]), pk_f16(acc[4 * c + 2], acc[4 * c + 3]));
     } else {
       SiteIO<S, LAYOUT>::store(out, cbc, s, Ls, k.plane, acc);
+    }
+  }
+  if (!MINV && k.cg) {
+    // the CG step: this 5D site's sum of squares (in FP64, components in
+    // order), then each checkerboard site's sum over its slices in slice
+    // order, so the per-site values do not depend on the launch shape
+    const bool live = active && (!k.skip || k.skip[(long)rc * k.skip_stride] == 0);
+    double ss = 0.0;
+    if (k.cg == 1) {
+#pragma unroll
+      for (int i = 0; i < 24; ++i) {
+        const double v = (double)Store<S>::to(Store<S>::from(acc[i]));   // as stored
+        ss += v * v;
+      }
+    } else if (live) {
+      T* rr = reinterpret_cast<T*>(k.cg_r) + (long)rc * k.rs_out;
+      T rv[24];
+      SiteIO<T, LAYOUT>::load(rr, cbc, s, Ls, k.plane, rv);
+      const T al = (T)k.cg_alpha[(long)rc * k.cg_alpha_stride];
+#pragma unroll
+      for (int i = 0; i < 24; ++i) {
+        rv[i] = rv[i] - al * acc[i];
+        ss += (double)rv[i] * (double)rv[i];
+      }
+      SiteIO<T, LAYOUT>::store(rr, cbc, s, Ls, k.plane, rv);
+    }
+    double* red = reinterpret_cast<double*>(snb + 8 * k.nsb);   // blockDim.x doubles
+    red[threadIdx.x] = live ? ss : 0.0;
+    __syncthreads();
+    if (live && s == 0) {
+      double t = 0.0;
+      for (int j = 0; j < Ls; ++j) t += red[threadIdx.x + j];
+      k.cg_site[(long)rc * Vh + cb] = t;
     }
   }
 }
@@ -365,6 +403,13 @@ int make_hopk(const qdwf_ctx* ctx, int prec, const HopArgs& a, const HopShape& s
   k->alpha = a.alpha; k->beta = a.beta;
   k->skip = a.skip;
   k->skip_stride = a.skip_stride;
+  k->cg = a.cg;
+  k->cg_r = a.cg_r;
+  k->cg_alpha = a.cg_alpha;
+  k->cg_alpha_stride = a.cg_alpha_stride;
+  k->cg_site = a.cg_site;
+  if (a.cg && (a.cg > 2 || !a.epi || a.npar != 1 || !a.cg_site || (a.cg == 2 && (!a.cg_r || !a.cg_alpha))))
+    return fail(QDWF_EINVAL, "fused CG step needs a one-parity hop with epilogue and its buffers");
   k->minv = MINV;
   if (MINV) {
     if (a.epi) return fail(QDWF_EINVAL, "fused M_ee^-1 takes no epilogue term");
@@ -377,8 +422,9 @@ int make_hopk(const qdwf_ctx* ctx, int prec, const HopArgs& a, const HopShape& s
   } else {
     for (int j = 0; j < 4; ++j) k->rpow[j] = 0.0;
   }
+  // links, neighbour table, then (fused CG step) one double per thread
   *lds = (size_t)8 * LinkStride<T>::v * k->nsb * sizeof(T) + (size_t)8 * k->nsb * sizeof(int) +
-                    (size_t)sh.lds_pad;
+         (a.cg ? (size_t)sh.threads * sizeof(double) : 0) + (size_t)sh.lds_pad;
   if (*lds > 64 * 1024) return fail(QDWF_EINVAL, "hop launch shape needs %zu bytes of LDS", *lds);
   *nblocks = nsblk * k->nrblk * a.npar;
   return QDWF_OK;

@@ -24,6 +24,17 @@ struct RhsState {
   int first;           // the next reliable update is the initial one
   int final;           // out of iterations: the next reliable update ends the solve
   int max_iter;        // iteration limit kept on the device (0: the host enforces it)
+  int xstep;           // the iteration's x step is due (running when |r|^2 was taken)
+};
+
+// The CG step a solver iteration fuses into the epilogue hop of M_pc or
+// M_pc^dag (HopArgs::cg and the fields after it).
+struct CgFuse {
+  int mode;
+  void* r;
+  const double* alpha;
+  int alpha_stride;
+  double* site;
 };
 
 inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -47,7 +58,7 @@ int apply_hop_parity(qdwf_ctx* ctx, int prec, int layout, int dagger, int out_pa
                      hipStream_t st, const int* skip = nullptr, int skip_stride = 0);
 int apply_mpc(qdwf_ctx* ctx, int prec, int layout, int dagger, void* out, const void* in,
               void* te1, void* te2, int nrhs, long rs, hipStream_t st,
-              const int* skip = nullptr, int skip_stride = 0);
+              const int* skip = nullptr, int skip_stride = 0, const CgFuse* cg = nullptr);
 int apply_mdagm(qdwf_ctx* ctx, int prec, int layout, void* out, const void* in, void* v,
                 void* te1, void* te2, int nrhs, long rs, hipStream_t st,
                 const int* skip = nullptr, int skip_stride = 0);

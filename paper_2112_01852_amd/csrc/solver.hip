@@ -41,36 +41,10 @@ __global__ void __launch_bounds__(RT) k_dot(const SA* __restrict__ a, const SB* 
   k_dot_body<SA, SB>(a, b, n, rsa, rsb, part, vec, blockIdx.x, gridDim.x, blockIdx.y, sh);
 }
 
-// <p, Ap> of the iteration: right-hand sides that are not running (waiting
-// for their reliable update, or finished) contribute a zero partial, which
-// k_alpha does not read
-template <class S>
-__global__ void __launch_bounds__(RT) k_dot_pap(const S* __restrict__ a, const S* __restrict__ b,
-                                                long n, double* __restrict__ part, int vec,
-                                                const RhsState* __restrict__ st) {
-  __shared__ double sh[RT];
-  if (st[blockIdx.y].status != ST_RUN) {
-    if (threadIdx.x == 0) part[(long)blockIdx.y * gridDim.x + blockIdx.x] = 0.0;
-    return;
-  }
-  k_dot_body<S, S>(a, b, n, n, n, part, vec, blockIdx.x, gridDim.x, blockIdx.y, sh);
-}
-
 __global__ void __launch_bounds__(RT) k_alpha(const double* __restrict__ part, int NB,
                                               RhsState* __restrict__ st) {
   __shared__ double sh[RT];
   k_alpha_body(part, NB, st, blockIdx.x, sh);
-}
-
-template <class SX, class SR, class SP>
-__global__ void __launch_bounds__(RT) k_update_xr(SX* __restrict__ x, SR* __restrict__ r,
-                                                  const SP* __restrict__ p,
-                                                  const SP* __restrict__ Ap, long n, long rs,
-                                                  const RhsState* __restrict__ st,
-                                                  double* __restrict__ part, int vec) {
-  __shared__ double sh[RT];
-  k_update_xr_body<SX, SR, SP>(x, r, p, Ap, n, rs, st, part, vec, blockIdx.x, gridDim.x,
-                               blockIdx.y, sh);
 }
 
 __global__ void __launch_bounds__(RT) k_beta(const double* __restrict__ part, int NB,
@@ -79,11 +53,17 @@ __global__ void __launch_bounds__(RT) k_beta(const double* __restrict__ part, in
   k_beta_body(part, NB, st, delta2, blockIdx.x, sh);
 }
 
-template <class SR, class SP>
-__global__ void __launch_bounds__(RT) k_update_p(const SR* __restrict__ r, SP* __restrict__ p,
-                                                 long n, long rs, const RhsState* __restrict__ st,
-                                                 int vec) {
-  k_update_p_body<SR, SP>(r, p, n, rs, st, vec, blockIdx.x, gridDim.x, blockIdx.y, nullptr);
+template <class SX, class SR, class SP>
+__global__ void __launch_bounds__(RT) k_update_px(SX* __restrict__ x, const SR* __restrict__ r,
+                                                  SP* __restrict__ p, long n,
+                                                  const RhsState* __restrict__ st, int vec) {
+  k_update_px_body<SX, SR, SP>(x, r, p, n, n, st, vec, blockIdx.x, gridDim.x, blockIdx.y);
+}
+
+__global__ void __launch_bounds__(RT) k_sum_sites(const double* __restrict__ v, long n,
+                                                  double* __restrict__ part) {
+  __shared__ double sh[RT];
+  k_sum_body(v, n, part, blockIdx.x, gridDim.x, blockIdx.y, sh);
 }
 
 template <class SX>
@@ -215,7 +195,7 @@ int apply_hop_parity(qdwf_ctx* ctx, int prec, int layout, int dagger, int out_pa
 // M_pc^dag applies A^dag once per site inside its hops anyway.
 int apply_mpc(qdwf_ctx* ctx, int prec, int layout, int dagger, void* out, const void* in,
               void* te1, void* te2, int nrhs, long rs, hipStream_t st, const int* skip,
-              int skip_stride) {
+              int skip_stride, const CgFuse* cg) {
   int rc;
   const int chi = dagger ? 0 : 1;
   if (ctx->g.Ls == 16) {
@@ -261,6 +241,13 @@ int apply_mpc(qdwf_ctx* ctx, int prec, int layout, int dagger, void* out, const 
   a.chi = chi;
   a.skip = skip;
   a.skip_stride = skip_stride;
+  if (cg) {
+    a.cg = cg->mode;
+    a.cg_r = cg->r;
+    a.cg_alpha = cg->alpha;
+    a.cg_alpha_stride = cg->alpha_stride;
+    a.cg_site = cg->site;
+  }
   return launch_hop(ctx, prec, layout, dagger, a, st);
 }
 
@@ -378,27 +365,45 @@ struct Cg {
   double* part() { return at<double>(L.off_part); }
   dim3 grid() const { return dim3(NB, nrhs); }
 
+  // One CG iteration with its vector work fused into the operator's hops:
+  //   v = M_pc p, with |v|^2 = <p, M_pc^dag M_pc p> summed by the hop;
+  //   alpha = |r|^2 / |v|^2;
+  //   r -= alpha M_pc^dag v inside the last hop (Ap is never stored), with
+  //   |r|^2 summed there;
+  //   beta; x += alpha p and p = r + beta p in one pass.
+  // The hops leave one sum per checkerboard site (in the room of Ap), which
+  // k_sum_sites reduces with a block count that depends only on the field size.
   int inner_iteration() {
     int rc;
     S* p = at<S>(L.off_p);
-    S* Ap = at<S>(L.off_ap);
+    S* v = at<S>(L.off_v);
+    R* x = at<R>(L.off_xl);
+    R* r = at<R>(L.off_rl);
+    double* site = at<double>(L.off_ap);
+    const long nsite = ctx->g.Vh;
+    const int NBs = reduce_blocks(nsite);
     // the workspace arrays start on 256-byte boundaries and n is a multiple of 24
-    const int vec_s = vec_ok<S>(n, {p, Ap}) ? 1 : 0;
-    const int vec_r = vec_ok<R>(n, {at<R>(L.off_xl), at<R>(L.off_rl)}) ? 1 : 0;
-    // the hops and p.Ap of a right-hand side that is not running do no work
-    static_assert(sizeof(RhsState) % sizeof(int) == 0, "RhsState is read as ints");
+    const int vec = vec_ok<S>(n, {p}) && vec_ok<R>(n, {x, r}) ? 1 : 0;
+    // the hops of a right-hand side that is not running do no work
+    static_assert(sizeof(RhsState) % sizeof(double) == 0, "RhsState is read as ints and doubles");
     const int* skip = reinterpret_cast<const int*>(
         reinterpret_cast<const char*>(d_state) + offsetof(RhsState, status));
-    if ((rc = apply_mdagm(ctx, inner, layout, Ap, p, at<S>(L.off_v), at<S>(L.off_t1),
-                          at<S>(L.off_t2), nrhs, n, st, skip, (int)(sizeof(RhsState) / sizeof(int)))))
+    const int sk = (int)(sizeof(RhsState) / sizeof(int));
+    CgFuse f1 = {1, nullptr, nullptr, 0, site};
+    if ((rc = apply_mpc(ctx, inner, layout, 0, v, p, at<S>(L.off_t1), at<S>(L.off_t2), nrhs, n, st,
+                        skip, sk, &f1)))
       return rc;
-    hipLaunchKernelGGL((k_dot_pap<S>), grid(), dim3(RT), 0, st, p, Ap, n, part(), vec_s, d_state);
-    hipLaunchKernelGGL(k_alpha, dim3(nrhs), dim3(RT), 0, st, part(), NB, d_state);
-    hipLaunchKernelGGL((k_update_xr<R, R, S>), grid(), dim3(RT), 0, st, at<R>(L.off_xl),
-                       at<R>(L.off_rl), p, Ap, n, n, d_state, part(), vec_s && vec_r);
-    hipLaunchKernelGGL(k_beta, dim3(nrhs), dim3(RT), 0, st, part(), NB, d_state, delta2);
-    hipLaunchKernelGGL((k_update_p<R, S>), grid(), dim3(RT), 0, st, at<R>(L.off_rl), p, n, n,
-                       d_state, vec_s && vec_r);
+    hipLaunchKernelGGL(k_sum_sites, dim3(NBs, nrhs), dim3(RT), 0, st, site, nsite, part());
+    hipLaunchKernelGGL(k_alpha, dim3(nrhs), dim3(RT), 0, st, part(), NBs, d_state);
+    const double* alpha = reinterpret_cast<const double*>(
+        reinterpret_cast<const char*>(d_state) + offsetof(RhsState, alpha));
+    CgFuse f2 = {2, r, alpha, (int)(sizeof(RhsState) / sizeof(double)), site};
+    if ((rc = apply_mpc(ctx, inner, layout, 1, at<S>(L.off_ap), v, at<S>(L.off_t1), at<S>(L.off_t2),
+                        nrhs, n, st, skip, sk, &f2)))
+      return rc;
+    hipLaunchKernelGGL(k_sum_sites, dim3(NBs, nrhs), dim3(RT), 0, st, site, nsite, part());
+    hipLaunchKernelGGL(k_beta, dim3(nrhs), dim3(RT), 0, st, part(), NBs, d_state, delta2);
+    hipLaunchKernelGGL((k_update_px<R, R, S>), grid(), dim3(RT), 0, st, x, r, p, n, d_state, vec);
     QDWF_HIP(hipGetLastError());
     hop_applications += 4;
     return QDWF_OK;
