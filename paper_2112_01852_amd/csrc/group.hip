@@ -2,6 +2,7 @@
 // kernels (grid-stride walks over the units of every member, each unit one
 // block of the single-solve kernels' work) and the captured round.
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 
 #include "cgbody.h"
@@ -30,6 +31,9 @@ struct GReq {
   RhsState* st;
   long n;                 // reals of a half field
   int NB;                 // reduction blocks
+  int NBs;                // blocks of the reduction of the per-site sums
+  long nsite;             // checkerboard sites (per-site sums of the fused CG step)
+  double* site;           // per-site sums, written by the fused hops
   int vec_s, vec_r;       // the inner vectors may be walked in aligned words
   int vec_b;              // the FP64 source may be walked in aligned words
   int scale;              // inner vectors kept at unit RMS (inner precision below FP64)
@@ -56,7 +60,7 @@ struct GLoc {
 };
 
 struct Table {
-  UnitHdr blas, one, hop16, hopg, loc;   // hop16: Ls = 16 members, hopg: the others
+  UnitHdr blas, one, hop16, hopg, loc, sites;   // hop16: Ls = 16 members, hopg: the others
   GReq req[kGroupMax];
   HopK hop_s[4][kGroupMax];   // M_pc^dag M_pc stages in the inner precision
   HopK hop_d[4][kGroupMax];   // the same in FP64 (reliable updates)
@@ -134,14 +138,13 @@ g_local(const Table* __restrict__ t, int which, int fp64, int want) {
     const GReq& r = t->req[j];                                \
     const int bx = u - h.start[j];
 
-// p . Ap of the running members
-template <class S>
-__global__ void __launch_bounds__(RT) g_dot_pap(const Table* __restrict__ t) {
+// The fused iteration's reductions of the per-site sums (|M_pc p|^2, then
+// |r|^2), alpha, beta and the x / p pass, as in the single-context solver.
+__global__ void __launch_bounds__(RT) g_sum_sites(const Table* __restrict__ t) {
   __shared__ double sh[RT];
-  GROUP_LOOP(blas)
+  GROUP_LOOP(sites)
     if (r.st->status != ST_RUN) continue;
-    k_dot_body<S, S>(reinterpret_cast<const S*>(r.p), reinterpret_cast<const S*>(r.ap), r.n, r.n,
-                     r.n, r.part, r.vec_s, bx, r.NB, 0, sh);
+    k_sum_body(r.site, r.nsite, r.part, bx, r.NBs, 0, sh);
   }
 }
 
@@ -149,17 +152,7 @@ __global__ void __launch_bounds__(RT) g_alpha(const Table* __restrict__ t) {
   __shared__ double sh[RT];
   for (int j = blockIdx.x; j < t->one.n; j += gridDim.x) {
     const GReq& r = t->req[j];
-    k_alpha_body(r.part, r.NB, r.st, 0, sh);
-  }
-}
-
-template <class S, class R>
-__global__ void __launch_bounds__(RT) g_update_xr(const Table* __restrict__ t) {
-  __shared__ double sh[RT];
-  GROUP_LOOP(blas)
-    k_update_xr_body<R, R, S>(reinterpret_cast<R*>(r.xl), reinterpret_cast<R*>(r.rl),
-                              reinterpret_cast<const S*>(r.p), reinterpret_cast<const S*>(r.ap),
-                              r.n, r.n, r.st, r.part, r.vec_s && r.vec_r, bx, r.NB, 0, sh);
+    k_alpha_body(r.part, r.NBs, r.st, 0, sh);
   }
 }
 
@@ -167,15 +160,16 @@ __global__ void __launch_bounds__(RT) g_beta(const Table* __restrict__ t) {
   __shared__ double sh[RT];
   for (int j = blockIdx.x; j < t->one.n; j += gridDim.x) {
     const GReq& r = t->req[j];
-    k_beta_body(r.part, r.NB, r.st, r.delta2, 0, sh);
+    k_beta_body(r.part, r.NBs, r.st, r.delta2, 0, sh);
   }
 }
 
 template <class S, class R>
-__global__ void __launch_bounds__(RT) g_update_p(const Table* __restrict__ t) {
+__global__ void __launch_bounds__(RT) g_update_px(const Table* __restrict__ t) {
   GROUP_LOOP(blas)
-    k_update_p_body<R, S>(reinterpret_cast<const R*>(r.rl), reinterpret_cast<S*>(r.p), r.n, r.n,
-                          r.st, r.vec_s && r.vec_r, bx, r.NB, 0, nullptr);
+    k_update_px_body<R, R, S>(reinterpret_cast<R*>(r.xl), reinterpret_cast<const R*>(r.rl),
+                              reinterpret_cast<S*>(r.p), r.n, r.n, r.st, r.vec_s && r.vec_r, bx,
+                              r.NB, 0);
   }
 }
 
@@ -239,11 +233,14 @@ bool words_ok(size_t elem, long n, std::initializer_list<const void*> ptrs) {
   return true;
 }
 
-size_t hop_lds_max(size_t real_bytes, size_t lstride) {
+// LDS of a grouped hop launch: the largest member's (cg: with the fused CG
+// step's one double per thread)
+size_t hop_lds_max(size_t real_bytes, size_t lstride, bool cg) {
   size_t m = 0;
   for (int Ls = kLsMin; Ls <= kLsMax; ++Ls) {
     const int nsb = 4 * (64 / Ls);
-    m = std::max(m, (size_t)8 * lstride * nsb * real_bytes + (size_t)8 * nsb * sizeof(int));
+    m = std::max(m, (size_t)8 * lstride * nsb * real_bytes + (size_t)8 * nsb * sizeof(int) +
+                        (cg ? 256 * sizeof(double) : 0));
   }
   return m;
 }
@@ -258,21 +255,25 @@ size_t local_lds_max(size_t real_bytes) {
 template <class S, class R, int LAYOUT>
 int record_round(const Table* t, int k, hipStream_t st) {
   typedef typename Store<S>::compute T;
-  const size_t lds_s = hop_lds_max(sizeof(T), LinkStride<T>::v);
-  const size_t lds_d = hop_lds_max(sizeof(double), LinkStride<double>::v);
+  const size_t lds_s = hop_lds_max(sizeof(T), LinkStride<T>::v, true);
+  const size_t lds_d = hop_lds_max(sizeof(double), LinkStride<double>::v, false);
   const size_t loc_s = local_lds_max(sizeof(T));
   const size_t loc_d = local_lds_max(sizeof(double));
   const dim3 hg(kHopGrid), hb(256), lg(kLocalGrid), lb(kLocalThreads), bg(kBlasGrid), bb(RT),
       og(kGroupMax);
-  auto mdagm = [&](auto stag, size_t lds, size_t llds, int fp64, int want) {
+  // M_pc (mid: between its two hops, for the fused CG step's reductions)
+  // and M_pc^dag
+  auto mpc = [&](auto stag, size_t lds, size_t llds, int fp64, int want) {
     typedef decltype(stag) P;
-    // M_pc: its first stage hands the second chi = (A/b) M_ee^-1 M_eo p
+    // its first stage hands the second chi = (A/b) M_ee^-1 M_eo p
     hipLaunchKernelGGL((g_hop<P, LAYOUT, false, true, true, true>), hg, hb, lds, st, t, 0, fp64, want);
     hipLaunchKernelGGL((g_hop<P, LAYOUT, false, false, false, false>), hg, hb, lds, st, t, 0, fp64, want);
     hipLaunchKernelGGL((g_local<P, LAYOUT>), lg, lb, llds, st, t, 0, fp64, want);
     hipLaunchKernelGGL((g_hop<P, LAYOUT, false, true, false, true>), hg, hb, lds, st, t, 1, fp64, want);
     hipLaunchKernelGGL((g_hop<P, LAYOUT, false, false, false, true>), hg, hb, lds, st, t, 1, fp64, want);
-    // M_pc^dag
+  };
+  auto mpc_dag = [&](auto stag, size_t lds, size_t llds, int fp64, int want) {
+    typedef decltype(stag) P;
     hipLaunchKernelGGL((g_hop<P, LAYOUT, true, true, true, false>), hg, hb, lds, st, t, 2, fp64, want);
     hipLaunchKernelGGL((g_hop<P, LAYOUT, true, false, false, false>), hg, hb, lds, st, t, 2, fp64, want);
     hipLaunchKernelGGL((g_local<P, LAYOUT>), lg, lb, llds, st, t, 1, fp64, want);
@@ -282,17 +283,20 @@ int record_round(const Table* t, int k, hipStream_t st) {
   for (int i = 0; i < k; ++i) {
     // reliable update of the members that asked for one (and the initial one)
     hipLaunchKernelGGL((g_fold_x<R>), bg, bb, 0, st, t);
-    mdagm(double(), lds_d, loc_d, 1, ST_UPDATE);
+    mpc(double(), lds_d, loc_d, 1, ST_UPDATE);
+    mpc_dag(double(), lds_d, loc_d, 1, ST_UPDATE);
     hipLaunchKernelGGL(g_resid, bg, bb, 0, st, t);
     hipLaunchKernelGGL(g_ru_decide, og, bb, 0, st, t);
     hipLaunchKernelGGL((g_ru_apply<S, R>), bg, bb, 0, st, t);
-    // one iteration of the running members
-    mdagm(S(), lds_s, loc_s, 0, ST_RUN);
-    hipLaunchKernelGGL((g_dot_pap<S>), bg, bb, 0, st, t);
+    // one iteration of the running members, its vector steps fused into
+    // the last hops of M_pc and M_pc^dag
+    mpc(S(), lds_s, loc_s, 0, ST_RUN);
+    hipLaunchKernelGGL(g_sum_sites, bg, bb, 0, st, t);
     hipLaunchKernelGGL(g_alpha, og, bb, 0, st, t);
-    hipLaunchKernelGGL((g_update_xr<S, R>), bg, bb, 0, st, t);
+    mpc_dag(S(), lds_s, loc_s, 0, ST_RUN);
+    hipLaunchKernelGGL(g_sum_sites, bg, bb, 0, st, t);
     hipLaunchKernelGGL(g_beta, og, bb, 0, st, t);
-    hipLaunchKernelGGL((g_update_p<S, R>), bg, bb, 0, st, t);
+    hipLaunchKernelGGL((g_update_px<S, R>), bg, bb, 0, st, t);
   }
   QDWF_HIP(hipGetLastError());
   return QDWF_OK;
@@ -333,8 +337,10 @@ int fill_hop(qdwf_ctx* ctx, int prec, const HopArgs& a, HopK* k) {
 
 // Hop and local arguments of M_pc^dag M_pc (stages 0..3) on one member:
 // out = M_pc^dag M_pc in with temporaries v, te1, te2 (half fields of prec).
+// With cg (the inner iteration), the last hops of M_pc and M_pc^dag take the
+// fused CG step instead (cg->mode is set per hop): out is then not written.
 int fill_mdagm(qdwf_ctx* ctx, int prec, const void* in, void* out, void* v, void* te1, void* te2,
-               HopK* hk[4], GLoc* lk[2]) {
+               HopK* hk[4], GLoc* lk[2], const CgFuse* cg = nullptr) {
   const Geom& g = ctx->g;
   const long rs = g.n5h * 24;
   const bool ls16 = g.Ls == 16;
@@ -377,6 +383,13 @@ int fill_mdagm(qdwf_ctx* ctx, int prec, const void* in, void* out, void* v, void
     b.alpha = al;
     b.beta = be;
     b.chi = dag ? 0 : 1;
+    if (cg) {
+      b.cg = dag ? 2 : 1;
+      b.cg_r = cg->r;
+      b.cg_alpha = cg->alpha;
+      b.cg_alpha_stride = cg->alpha_stride;
+      b.cg_site = cg->site;
+    }
     if ((rc = fill_hop(ctx, prec, b, hk[2 * dag + 1]))) return rc;
   }
   return QDWF_OK;
@@ -443,8 +456,9 @@ GroupEngine::~GroupEngine() {
 int GroupEngine::set_members(const GroupMember* m, int n, hipStream_t st) {
   if (n < 0 || n > kGroupMax) return fail(QDWF_EINVAL, "%d members, at most %d", n, kGroupMax);
   Table& T = *reinterpret_cast<Table*>(staging_);
-  T.blas.n = T.one.n = T.hop16.n = T.hopg.n = T.loc.n = n;
-  T.blas.start[0] = T.one.start[0] = T.hop16.start[0] = T.hopg.start[0] = T.loc.start[0] = 0;
+  T.blas.n = T.one.n = T.hop16.n = T.hopg.n = T.loc.n = T.sites.n = n;
+  T.blas.start[0] = T.one.start[0] = T.hop16.start[0] = T.hopg.start[0] = T.loc.start[0] =
+      T.sites.start[0] = 0;
   const size_t ps = prec_bytes(inner_);
   const size_t rsz = inner_ == QDWF_F64 ? 8 : 4;
   int rc;
@@ -460,6 +474,10 @@ int GroupEngine::set_members(const GroupMember* m, int n, hipStream_t st) {
     r.st = m[j].st;
     r.n = n5;
     r.NB = reduce_blocks(n5);
+    r.nsite = g.Vh;
+    r.NBs = reduce_blocks(g.Vh);
+    // the per-site sums take the room of Ap, which the fused iteration never stores
+    r.site = reinterpret_cast<double*>(w + L.off_ap);
     r.xl = w + L.off_xl;
     r.rl = w + L.off_rl;
     r.p = w + L.off_p;
@@ -479,7 +497,10 @@ int GroupEngine::set_members(const GroupMember* m, int n, hipStream_t st) {
     r.delta2 = inner_ == QDWF_F64 ? 0.0 : delta * delta;
     HopK* hs[4] = {&T.hop_s[0][j], &T.hop_s[1][j], &T.hop_s[2][j], &T.hop_s[3][j]};
     GLoc* ls[2] = {&T.loc_s[0][j], &T.loc_s[1][j]};
-    if ((rc = fill_mdagm(c, inner_, r.p, r.ap, w + L.off_v, w + L.off_t1, w + L.off_t2, hs, ls)))
+    const double* alpha = reinterpret_cast<const double*>(reinterpret_cast<const char*>(r.st) +
+                                                          offsetof(RhsState, alpha));
+    const CgFuse cg = {0, r.rl, alpha, 0, r.site};
+    if ((rc = fill_mdagm(c, inner_, r.p, r.ap, w + L.off_v, w + L.off_t1, w + L.off_t2, hs, ls, &cg)))
       return rc;
     HopK* hd[4] = {&T.hop_d[0][j], &T.hop_d[1][j], &T.hop_d[2][j], &T.hop_d[3][j]};
     GLoc* ld[2] = {&T.loc_d[0][j], &T.loc_d[1][j]};
@@ -487,6 +508,7 @@ int GroupEngine::set_members(const GroupMember* m, int n, hipStream_t st) {
       return rc;
     const int gpw = 64 / g.Ls;
     T.blas.start[j + 1] = T.blas.start[j] + r.NB;
+    T.sites.start[j + 1] = T.sites.start[j] + r.NBs;
     T.one.start[j + 1] = j + 1;
     const int hop_units = (g.Vh + 4 * gpw - 1) / (4 * gpw);
     T.hop16.start[j + 1] = T.hop16.start[j] + (g.Ls == 16 ? hop_units : 0);
