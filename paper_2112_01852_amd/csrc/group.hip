@@ -475,7 +475,7 @@ int GroupEngine::set_members(const GroupMember* m, int n, hipStream_t st) {
     r.n = n5;
     r.NB = reduce_blocks(n5);
     r.nsite = g.Vh;
-    r.NBs = reduce_blocks(g.Vh);
+    r.NBs = site_blocks(g.Vh);
     // the per-site sums take the room of Ap, which the fused iteration never stores
     r.site = reinterpret_cast<double*>(w + L.off_ap);
     r.xl = w + L.off_xl;

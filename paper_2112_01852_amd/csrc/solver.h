@@ -52,6 +52,7 @@ struct Layout {
 Layout solver_layout(long n, int nrhs, int inner);
 
 int reduce_blocks(long n);
+int site_blocks(long nsite);
 // skip, skip_stride: per right-hand-side flags of the hops (HopArgs::skip)
 int apply_hop_parity(qdwf_ctx* ctx, int prec, int layout, int dagger, int out_par, void* out,
                      const void* in, const void* z, double scale, int nrhs, long rs,

@@ -158,6 +158,17 @@ __global__ void k_copy64(double* __restrict__ d, const S* __restrict__ s, long n
 
 }  // namespace
 
+// Blocks of the reduction of per-site sums (a few values per thread: the
+// sums are few and the reduction sits between two hops of an iteration).
+// Never more than reduce_blocks gives for the 2 x 24 x Ls x sites reals of
+// the same field, whose partials share the room.
+int site_blocks(long nsite) {
+  long nb = (nsite + 1023) / 1024;
+  if (nb < 1) nb = 1;
+  if (nb > 2048) nb = 2048;
+  return (int)nb;
+}
+
 int reduce_blocks(long n) {
   long nb = (n + 8191) / 8192;
   if (nb < 1) nb = 1;
@@ -381,7 +392,7 @@ struct Cg {
     R* r = at<R>(L.off_rl);
     double* site = at<double>(L.off_ap);
     const long nsite = ctx->g.Vh;
-    const int NBs = reduce_blocks(nsite);
+    const int NBs = site_blocks(nsite);
     // the workspace arrays start on 256-byte boundaries and n is a multiple of 24
     const int vec = vec_ok<S>(n, {p}) && vec_ok<R>(n, {x, r}) ? 1 : 0;
     // the hops of a right-hand side that is not running do no work
