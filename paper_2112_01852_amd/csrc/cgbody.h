@@ -10,6 +10,7 @@
 
 #include <initializer_list>
 
+#include "cgtypes.h"
 #include "common.h"
 #include "solver.h"
 

@@ -254,9 +254,10 @@ struct HopArgs {
   // sum of squares over the Ls slices of checkerboard site i of rhs r:
   //   cg = 1: of the output as stored;
   //   cg = 2: the output is not stored; cg_r -= alpha_r * output instead
-  //     (alpha_r = cg_alpha[r * cg_alpha_stride]; cg_r in the compute type,
-  //     double for FP64 storage and float otherwise, in the output's layout
-  //     and rhs stride), and the sums are of the updated cg_r.
+  //     (alpha_r = cg_alpha[r * cg_alpha_stride]; cg_r in FP16 for FP16
+  //     storage, else in the compute type: double for FP64 storage and
+  //     float otherwise; in the output's layout and rhs stride), and the
+  //     sums are of the updated cg_r as stored.
   // Rhs whose skip flag is set are left alone.
   int cg;
   void* cg_r;

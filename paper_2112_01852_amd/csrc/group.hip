@@ -39,7 +39,7 @@ struct GReq {
   int scale;              // inner vectors kept at unit RMS (inner precision below FP64)
   int max_iter;
   void* xl;               // inner solution increment (R)
-  void* rl;               // inner residual (R)
+  void* rl;               // inner residual (ResidStore of S)
   void* p;                // search direction (S)
   void* ap;               // M_pc^dag M_pc p (S)
   double* xh;             // FP64 solution
@@ -166,8 +166,9 @@ __global__ void __launch_bounds__(RT) g_beta(const Table* __restrict__ t) {
 
 template <class S, class R>
 __global__ void __launch_bounds__(RT) g_update_px(const Table* __restrict__ t) {
+  typedef typename ResidStore<S>::t RR;
   GROUP_LOOP(blas)
-    k_update_px_body<R, R, S>(reinterpret_cast<R*>(r.xl), reinterpret_cast<const R*>(r.rl),
+    k_update_px_body<R, RR, S>(reinterpret_cast<R*>(r.xl), reinterpret_cast<const RR*>(r.rl),
                               reinterpret_cast<S*>(r.p), r.n, r.n, r.st, r.vec_s && r.vec_r, bx,
                               r.NB, 0);
   }
@@ -200,8 +201,9 @@ __global__ void __launch_bounds__(RT) g_ru_decide(const Table* __restrict__ t) {
 
 template <class S, class R>
 __global__ void __launch_bounds__(RT) g_ru_apply(const Table* __restrict__ t) {
+  typedef typename ResidStore<S>::t RR;
   GROUP_LOOP(blas)
-    k_ru_apply_body<R, S>(r.rh, reinterpret_cast<R*>(r.rl), reinterpret_cast<S*>(r.p), r.n, r.n,
+    k_ru_apply_body<RR, S>(r.rh, reinterpret_cast<RR*>(r.rl), reinterpret_cast<S*>(r.p), r.n, r.n,
                           r.st, bx, r.NB, 0, nullptr);
   }
 }
@@ -488,7 +490,7 @@ int GroupEngine::set_members(const GroupMember* m, int n, hipStream_t st) {
     r.ax = reinterpret_cast<double*>(w + L.off_ax);
     r.part = reinterpret_cast<double*>(w + L.off_part);
     r.vec_s = words_ok(ps, n5, {r.p, r.ap}) ? 1 : 0;
-    r.vec_r = words_ok(rsz, n5, {r.xl, r.rl}) ? 1 : 0;
+    r.vec_r = words_ok(rsz, n5, {r.xl}) && words_ok(inner_ == QDWF_F16 ? 2 : rsz, n5, {r.rl}) ? 1 : 0;
     r.vec_b = words_ok(8, n5, {r.b}) ? 1 : 0;
     r.scale = inner_ != QDWF_F64 ? 1 : 0;
     r.max_iter = m[j].max_iter > 0 ? m[j].max_iter : 20000;

@@ -22,6 +22,7 @@
 
 #include <type_traits>
 
+#include "cgtypes.h"
 #include "common.h"
 #include "hopcore.h"
 #include "pk16.h"
@@ -353,16 +354,18 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
         ss += v * v;
       }
     } else if (live) {
-      T* rr = reinterpret_cast<T*>(k.cg_r) + (long)rc * k.rs_out;
+      typedef typename ResidStore<S>::t RS;
+      RS* rr = reinterpret_cast<RS*>(k.cg_r) + (long)rc * k.rs_out;
       T rv[24];
-      SiteIO<T, LAYOUT>::load(rr, cbc, s, Ls, k.plane, rv);
+      SiteIO<RS, LAYOUT>::load(rr, cbc, s, Ls, k.plane, rv);
       const T al = (T)k.cg_alpha[(long)rc * k.cg_alpha_stride];
 #pragma unroll
       for (int i = 0; i < 24; ++i) {
         rv[i] = rv[i] - al * acc[i];
-        ss += (double)rv[i] * (double)rv[i];
+        const double v = (double)Store<RS>::to(Store<RS>::from(rv[i]));   // as stored
+        ss += v * v;
       }
-      SiteIO<T, LAYOUT>::store(rr, cbc, s, Ls, k.plane, rv);
+      SiteIO<RS, LAYOUT>::store(rr, cbc, s, Ls, k.plane, rv);
     }
     double* red = reinterpret_cast<double*>(snb + 8 * k.nsb);   // blockDim.x doubles
     red[threadIdx.x] = live ? ss : 0.0;

@@ -328,6 +328,7 @@ Layout solver_layout(long n, int nrhs, int inner) {
   Layout L;
   const size_t sS = prec_bytes(inner);
   const size_t sR = inner == QDWF_F64 ? 8 : 4;
+  const size_t sRl = inner == QDWF_F16 ? 2 : sR;   // the residual's storage (ResidStore)
   const size_t v64 = al256(8 * (size_t)n * nrhs);
   const size_t vR = al256(sR * (size_t)n * nrhs);
   const size_t vS = al256(sS * (size_t)n * nrhs);
@@ -338,7 +339,7 @@ Layout solver_layout(long n, int nrhs, int inner) {
   L.off_t1h = o; o += v64;
   L.off_t2h = o; o += v64;
   L.off_xl = o; o += vR;
-  L.off_rl = o; o += vR;
+  L.off_rl = o; o += al256(sRl * (size_t)n * nrhs);
   L.off_p = o; o += vS;
   L.off_ap = o; o += vS;
   L.off_v = o; o += vS;
@@ -356,6 +357,7 @@ namespace {
 
 template <class S, class R>
 struct Cg {
+  typedef typename ResidStore<S>::t RR;   // storage of the inner residual
   qdwf_ctx* ctx;
   hipStream_t st;
   int layout, inner, nrhs;
@@ -389,12 +391,12 @@ struct Cg {
     S* p = at<S>(L.off_p);
     S* v = at<S>(L.off_v);
     R* x = at<R>(L.off_xl);
-    R* r = at<R>(L.off_rl);
+    RR* r = at<RR>(L.off_rl);
     double* site = at<double>(L.off_ap);
     const long nsite = ctx->g.Vh;
     const int NBs = site_blocks(nsite);
     // the workspace arrays start on 256-byte boundaries and n is a multiple of 24
-    const int vec = vec_ok<S>(n, {p}) && vec_ok<R>(n, {x, r}) ? 1 : 0;
+    const int vec = vec_ok<S>(n, {p}) && vec_ok<R>(n, {x}) && vec_ok<RR>(n, {r}) ? 1 : 0;
     // the hops of a right-hand side that is not running do no work
     static_assert(sizeof(RhsState) % sizeof(double) == 0, "RhsState is read as ints and doubles");
     const int* skip = reinterpret_cast<const int*>(
@@ -414,7 +416,7 @@ struct Cg {
       return rc;
     hipLaunchKernelGGL(k_sum_sites, dim3(NBs, nrhs), dim3(RT), 0, st, site, nsite, part());
     hipLaunchKernelGGL(k_beta, dim3(nrhs), dim3(RT), 0, st, part(), NBs, d_state, delta2);
-    hipLaunchKernelGGL((k_update_px<R, R, S>), grid(), dim3(RT), 0, st, x, r, p, n, d_state, vec);
+    hipLaunchKernelGGL((k_update_px<R, RR, S>), grid(), dim3(RT), 0, st, x, r, p, n, d_state, vec);
     QDWF_HIP(hipGetLastError());
     hop_applications += 4;
     return QDWF_OK;
@@ -435,7 +437,7 @@ struct Cg {
     hipLaunchKernelGGL(k_resid, grid(), dim3(RT), 0, st, b, ax, rh, n, rs_b, n, part());
     hipLaunchKernelGGL(k_ru_decide, dim3(nrhs), dim3(RT), 0, st, part(), NB, d_state, tol2,
                        (double)n, inner != QDWF_F64 ? 1 : 0, first ? 1 : 0);
-    hipLaunchKernelGGL((k_ru_apply<R, S>), grid(), dim3(RT), 0, st, rh, at<R>(L.off_rl),
+    hipLaunchKernelGGL((k_ru_apply<RR, S>), grid(), dim3(RT), 0, st, rh, at<RR>(L.off_rl),
                        at<S>(L.off_p), n, n, d_state);
     QDWF_HIP(hipGetLastError());
     return QDWF_OK;
