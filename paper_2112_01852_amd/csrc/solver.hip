@@ -2,8 +2,9 @@
 // M_pc^dag M_pc, for several right-hand sides at once, with
 //   * plain FP64 CG (inner precision FP64), or
 //   * reliable-update mixed-precision CG: the inner iteration runs its Dslash
-//     on FP32 arithmetic with FP32, FP16 or BF16 storage of p, Ap and the
-//     operator temporaries, r and the solution increment in FP32, all dot
+//     on FP32 arithmetic with FP32, FP16 or BF16 storage of p and the
+//     operator temporaries, r in FP32 (in FP16 with FP16 storage) and the
+//     solution increment in FP32, all dot
 //     products accumulated in FP64; when the inner residual has dropped by
 //     delta since the last update (or reached the target) the increment is
 //     folded into the FP64 solution and the residual is recomputed in FP64
