@@ -131,3 +131,63 @@ def test_not_converged_and_nan_are_reported(setup):
     bad[np.unravel_index(np.argmax(np.abs(b)), b.shape)] = np.nan
     rc, st, x = _solve(q, D, bad, 1)
     assert rc == q.QDWF_ENAN
+
+
+@pytest.mark.parametrize("inner", [0, 2])
+def test_fused_cg_step_independent_of_hop_shape(q, tmp_path, inner):
+    """The hops carry the CG step's sums as one value per checkerboard site,
+    so the solve must be bitwise the same for every launch shape of the hop:
+    fewer threads per block, and blocks that hold two or four right-hand
+    sides (whose lanes update r only while their own right-hand side runs;
+    the three sources below pause for reliable updates at different
+    iterations). Checked against the oracle's residual as well."""
+    import os
+    import torch
+    L, Ls, nrhs = (4, 4, 4, 8), 16, 3
+    a = cpu.Action(L=L, Ls=Ls, **MOBIUS)
+    U = I.gauge_field(L, "smooth", 3100, eps=0.3)
+    bs = np.stack([cpu.restrict(I.gaussian_spinor(L, Ls, 3101 + j), L, 1) for j in range(nrhs)])
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+    def run(cache_shape=None, threads=None):
+        env = {}
+        if cache_shape is not None:
+            env["QDWF_TUNE_CACHE"] = str(tmp_path / f"shape_{cache_shape[0]}_{cache_shape[1]}.jsonl")
+        if threads is not None:
+            env["QDWF_HOP_THREADS"] = str(threads)
+        old = {k: os.environ.get(k) for k in env}
+        os.environ.update(env)
+        try:
+            D = q.Dirac(L, Ls, **MOBIUS)
+            if cache_shape is not None:
+                tr = q.qdwf_traversal(D.ctx)
+                t = tr["tile"]
+                with open(env["QDWF_TUNE_CACHE"], "w") as f:
+                    for prec in {inner, q.QDWF_F64}:
+                        for dag in (0, 1):
+                            key = (f"{L[0]}x{L[1]}x{L[2]}x{L[3]}_Ls{Ls}_p{prec}_l{q.QDWF_RIRI}_d{dag}"
+                                   f"_n{nrhs}_t{t[0]}.{t[1]}.{t[2]}.{t[3]}_o{tr['split']}.{tr['sweep']}_{arch}")
+                            f.write(f'{{"key": "{key}", "threads": {cache_shape[0]}, "nrb": {cache_shape[1]}, '
+                                    f'"xcd": 1, "lds_pad": 0, "sweep": 0, "ms": 1.0}}\n')
+                got = q.qdwf_tuned_shape(D.ctx, inner, q.QDWF_RIRI, 1, nrhs)
+                assert (got["threads"], got["nrb"]) == cache_shape, got
+            D.set_gauge(U)
+            rc, st, x = _solve(q, D, bs, inner, layout=q.QDWF_RIRI, nrhs=nrhs, use_graph=0)
+            D.close()
+        finally:
+            for k, v in old.items():
+                if v is None:
+                    del os.environ[k]
+                else:
+                    os.environ[k] = v
+        assert rc == q.QDWF_OK and st.converged == nrhs
+        return st, x
+
+    st0, x0 = run()
+    for j in range(nrhs):
+        r = bs[j] - cpu.mpc(a, U, cpu.mpc(a, U, x0[j]), dagger=True)
+        assert np.linalg.norm(r) / np.linalg.norm(bs[j]) <= 1.5e-10
+    for kw in (dict(threads=128), dict(cache_shape=(256, 2)), dict(cache_shape=(256, 4))):
+        st, x = run(**kw)
+        assert st.iterations == st0.iterations, kw
+        assert np.array_equal(x, x0), f"the solve depends on the hop launch shape {kw}"
