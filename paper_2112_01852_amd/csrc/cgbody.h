@@ -1,5 +1,5 @@
-// Bodies of the CG vector kernels (reductions, alpha/beta, the x/r and p
-// updates, the reliable-update steps), shared by the launches over one
+// Bodies of the CG vector kernels (reductions, alpha/beta, the x/p pass of
+// the fused iteration, the reliable-update steps), shared by the launches over one
 // context's right-hand sides (solver.hip) and the grouped launches over many
 // requests (group.hip). Each body does the work of one block `bx` of `NB`
 // for right-hand side `q` (the per-right-hand-side scalar steps take only q);
@@ -121,7 +121,7 @@ __device__ inline void k_dot_body(const SA* __restrict__ a, const SB* __restrict
   if (threadIdx.x == 0) part[(long)r * NB + bx] = t;
 }
 
-// alpha = rr / <p, Ap>
+// alpha = rr / <p, Ap>, <p, Ap> = |M_pc p|^2 from the partials
 __device__ inline void k_alpha_body(const double* __restrict__ part, int NB,
                                               RhsState* __restrict__ st,
     int q, double* sh) {
@@ -137,62 +137,6 @@ __device__ inline void k_alpha_body(const double* __restrict__ part, int NB,
     return;
   }
   s.alpha = s.rr / pAp;
-}
-
-// x += alpha p ; r -= alpha Ap ; partial |r|^2
-template <class SX, class SR, class SP>
-__device__ inline void k_update_xr_body(SX* __restrict__ x, SR* __restrict__ r,
-                                                  const SP* __restrict__ p,
-                                                  const SP* __restrict__ Ap, long n, long rs,
-                                                  const RhsState* __restrict__ st,
-                                                  double* __restrict__ part, int vec,
-    int bx, int NB, int q, double* sh) {
-  typedef typename Store<SR>::compute T;
-  const RhsState& s = st[q];
-  if (s.status != ST_RUN) {
-    if (threadIdx.x == 0) part[(long)q * NB + bx] = 0.0;
-    return;
-  }
-  const T al = (T)s.alpha;
-  SX* xr = x + (long)q * rs;
-  SR* rr = r + (long)q * rs;
-  const SP* pr = p + (long)q * rs;
-  const SP* ar = Ap + (long)q * rs;
-  double acc = 0;
-  constexpr int E = ChunkWidth<SX, SR, SP>::e;
-  const long nt = vec ? n / TILE : 0;
-  const int lane = threadIdx.x & 63;
-  const long t1 = nt * (bx + 1) / NB;   // this block's contiguous range of tiles
-  for (long t = nt * bx / NB + (threadIdx.x >> 6); t < t1; t += RT / 64) {
-#pragma unroll
-    for (int j = 0; j < 8 / E; ++j) {
-      const long i = t * TILE + j * 64 * E + lane * E;
-      T pv[E], av[E], xv[E], rv[E];
-      Chunk<SP, E>::ld(pr + i, pv);
-      Chunk<SP, E>::ld(ar + i, av);
-      Chunk<SX, E>::ld(xr + i, xv);
-      Chunk<SR, E>::ld(rr + i, rv);
-#pragma unroll
-      for (int k = 0; k < E; ++k) {
-        xv[k] = xv[k] + al * pv[k];
-        rv[k] = rv[k] - al * av[k];
-      }
-      Chunk<SX, E>::st(xr + i, xv);
-      Chunk<SR, E>::st(rr + i, rv);
-#pragma unroll
-      for (int k = 0; k < E; ++k) acc += (double)rv[k] * (double)rv[k];
-    }
-  }
-  for (long i = TILE * nt + (long)bx * RT + threadIdx.x; i < n; i += (long)NB * RT) {
-    const T pv = (T)Store<SP>::to(pr[i]);
-    const T av = (T)Store<SP>::to(ar[i]);
-    xr[i] = Store<SX>::from((T)Store<SX>::to(xr[i]) + al * pv);
-    const T rv = (T)Store<SR>::to(rr[i]) - al * av;
-    rr[i] = Store<SR>::from(rv);
-    acc += (double)rv * (double)rv;
-  }
-  const double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) part[(long)q * NB + bx] = t;
 }
 
 // beta = rr_new / rr ; decide whether a reliable update is due
@@ -218,38 +162,6 @@ __device__ inline void k_beta_body(const double* __restrict__ part, int NB,
     s.status = ST_UPDATE;
     s.final = 1;
   }
-}
-
-// p = r + beta p
-template <class SR, class SP>
-__device__ inline void k_update_p_body(const SR* __restrict__ r, SP* __restrict__ p,
-                                                 long n, long rs, const RhsState* __restrict__ st,
-                                                 int vec,
-    int bx, int NB, int q, double* sh) {
-  typedef typename Store<SR>::compute T;
-  const RhsState& s = st[q];
-  if (s.status != ST_RUN) return;
-  const T be = (T)s.beta;
-  const SR* rr = r + (long)q * rs;
-  SP* pr = p + (long)q * rs;
-  constexpr int E = ChunkWidth<SR, SP>::e;
-  const long nt = vec ? n / TILE : 0;
-  const int lane = threadIdx.x & 63;
-  const long t1 = nt * (bx + 1) / NB;   // this block's contiguous range of tiles
-  for (long t = nt * bx / NB + (threadIdx.x >> 6); t < t1; t += RT / 64) {
-#pragma unroll
-    for (int j = 0; j < 8 / E; ++j) {
-      const long i = t * TILE + j * 64 * E + lane * E;
-      T rv[E], pv[E];
-      Chunk<SR, E>::ld(rr + i, rv);
-      Chunk<SP, E>::ld(pr + i, pv);
-#pragma unroll
-      for (int k = 0; k < E; ++k) pv[k] = rv[k] + be * pv[k];
-      Chunk<SP, E>::st(pr + i, pv);
-    }
-  }
-  for (long i = TILE * nt + (long)bx * RT + threadIdx.x; i < n; i += (long)NB * RT)
-    pr[i] = Store<SP>::from((T)Store<SR>::to(rr[i]) + be * (T)Store<SP>::to(pr[i]));
 }
 
 // The vector step of the fused iteration, after r and |r|^2 came from the
