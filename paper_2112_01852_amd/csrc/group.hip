@@ -41,7 +41,7 @@ struct GReq {
   void* xl;               // inner solution increment (R)
   void* rl;               // inner residual (ResidStore of S)
   void* p;                // search direction (S)
-  void* ap;               // M_pc^dag M_pc p (S)
+  void* ap;               // output of M_pc^dag M_pc, which the fused step never stores
   double* xh;             // FP64 solution
   const double* b;        // FP64 source
   double* rh;             // FP64 true residual
@@ -489,7 +489,7 @@ int GroupEngine::set_members(const GroupMember* m, int n, hipStream_t st) {
     r.rh = reinterpret_cast<double*>(w + L.off_rh);
     r.ax = reinterpret_cast<double*>(w + L.off_ax);
     r.part = reinterpret_cast<double*>(w + L.off_part);
-    r.vec_s = words_ok(ps, n5, {r.p, r.ap}) ? 1 : 0;
+    r.vec_s = words_ok(ps, n5, {r.p}) ? 1 : 0;
     r.vec_r = words_ok(rsz, n5, {r.xl}) && words_ok(inner_ == QDWF_F16 ? 2 : rsz, n5, {r.rl}) ? 1 : 0;
     r.vec_b = words_ok(8, n5, {r.b}) ? 1 : 0;
     r.scale = inner_ != QDWF_F64 ? 1 : 0;
