@@ -197,6 +197,9 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
   const T cb_ = (T)k.c_over_b;
   const T cm = cb_ * wm, cp = cb_ * wp;
   const T* lks = su + sl * 8 * LSTR;
+  // the same factors as FP16 pairs, for the packed path's A
+  const uint32_t cmh = PK ? pk_f16((float)cm, (float)cm) : 0u;
+  const uint32_t cph = PK ? pk_f16((float)cp, (float)cp) : 0u;
 
   T acc[24];
   // direction D uses the buffer loaded two steps earlier and refills it with
@@ -220,19 +223,22 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
       if constexpr (D < 6) load_pk(nbs[(D + 2) * k.nsb], buf);
       uint32_t h[6];
       if constexpr (APPLY_A) {
-        T v[24], x[24];
+        // chi / b = psi + (c/b) (P+ psi_{s-1} + P- psi_{s+1}) in packed FP16:
+        // upper spins (words 0-5) from slice s-1, lower (6-11) from s+1 (a
+        // DPP row rotate at Ls = 16, a cross-lane permute otherwise)
+        auto from_m = [&](uint32_t v) -> uint32_t {
+          if constexpr (DPP16) return (uint32_t)dpp_ror<1>((int)v);
+          else return (uint32_t)__shfl((int)v, sh.src_m, 64);
+        };
+        auto from_p = [&](uint32_t v) -> uint32_t {
+          if constexpr (DPP16) return (uint32_t)dpp_ror<15>((int)v);
+          else return (uint32_t)__shfl((int)v, sh.src_p, 64);
+        };
+        uint32_t x[12];
 #pragma unroll
-        for (int i = 0; i < 12; ++i) {
-          v[2 * i] = f16_lo(w[i]);
-          v[2 * i + 1] = f16_hi(w[i]);
-        }
-#pragma unroll
-        for (int i = 0; i < 24; ++i) x[i] = v[i];
-        shift_s<1, 15>(sh, cm, cp, x, v);
-        T hf[12];
-        project<MU, SG>(v, hf);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) h[i] = pk_f16(hf[2 * i], hf[2 * i + 1]);
+        for (int i = 0; i < 12; ++i)
+          x[i] = i < 6 ? pk_fma(cmh, from_m(w[i]), w[i]) : pk_fma(cph, from_p(w[i]), w[i]);
+        project_pk<MU, SG>(x, h);
       } else {
         project_pk<MU, SG>(w, h);
       }

@@ -38,6 +38,11 @@ template <int CR, int CI> __device__ inline uint32_t pk_cadd(uint32_t aw, uint32
   else return as_u32(a + (half2v){b.y, -b.x});                          // (a.re + b.im, a.im - b.re)
 }
 
+// a * b + c on both halves, one FP16 rounding each (v_pk_fma_f16)
+__device__ inline uint32_t pk_fma(uint32_t a, uint32_t b, uint32_t c) {
+  return as_u32(__builtin_elementwise_fma(as_h2(a), as_h2(b), as_h2(c)));
+}
+
 // c + a.lo b.lo + a.hi b.hi in FP32
 __device__ inline float dot2(uint32_t a, uint32_t b, float c) {
   return __builtin_amdgcn_fdot2(as_h2(a), as_h2(b), c, false);
