@@ -72,7 +72,7 @@ HopShape default_shape(const qdwf_ctx* ctx, int prec, int nrhs) {
   // traversal in FP32 with 16- and 32-wide rows (one and two blocks of 8
   // waves per CU); slower with 24-wide ones (6 waves per CU), in BF16
   // storage, and in FP16 storage since the checkerboard kernel keeps FP16
-  // neighbours packed (32^4 x 16 D 0.76 against 0.84 ms); the tuner tries
+  // neighbours packed (32^4 x 16 D 0.73 against 0.84 ms); the tuner tries
   // it wherever it applies
   const int Lx = ctx->g.L[0];
   sh.sweep = (prec == QDWF_F32 && (Lx == 16 || Lx == 32)) ? 1 : 0;
