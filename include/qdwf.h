@@ -283,8 +283,11 @@ int qdwf_dot_noalloc(qdwf_ctx* ctx, double* out, const void* x, const void* y, i
                      int prec, int layout, int nrhs, void* stream);
 
 /* ---- solver ----------------------------------------------------------- */
-/* Solves for nrhs right-hand sides at once (links loaded once per tile for
- * all of them). x, b are FP64 fields in params->layout: odd half fields for
+/* Solves for nrhs right-hand sides at once: every launch of the solve covers
+ * all of them (the hop takes one right-hand side per block unless the tuner
+ * chose blocks that share their staged links between several), and a
+ * right-hand side that has converged or waits for its reliable update skips
+ * its hops. x, b are FP64 fields in params->layout: odd half fields for
  * QDWF_SYS_NORMAL_PC, full fields for QDWF_SYS_FULL. inner_prec = QDWF_F64
  * runs plain FP64 CG; any other value runs CG with that inner precision and
  * FP64 reliable updates (true residual recomputed in FP64; x accumulated in
