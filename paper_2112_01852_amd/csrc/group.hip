@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstring>
+#include <type_traits>
 
 #include "cgbody.h"
 #include "group.h"
@@ -92,7 +93,10 @@ __device__ inline int member_of(const UnitHdr& h, int u) {
 // permute form of 16-bit storage two, the others as the single-context hop.
 template <class S, int LAYOUT, bool DPP16> struct GroupWaves {
   static constexpr int v =
-      sizeof(S) == 8 ? 1 : (sizeof(S) == 2 && !DPP16) ? 2 : WavesPerEU<S, LAYOUT, DPP16>::v;
+      sizeof(S) == 8 ? 1
+      : (sizeof(S) == 2 && !DPP16) ? 2
+      : (std::is_same<S, float>::value && LAYOUT == QDWF_RIRI) ? 3   // one-parity hops, as for one context
+      : WavesPerEU<S, LAYOUT, DPP16>::v;
 };
 
 template <class S, int LAYOUT, bool DAG, bool DPP16, bool MINV, bool CHI>
