@@ -54,7 +54,8 @@ struct HopK {
 
 // Target occupancy (waves per SIMD) the register allocator plans for: two for
 // 32- and 64-bit storage, whose arithmetic needs the registers to keep two
-// directions' neighbour loads in flight; four for the packed FP16 path
+// directions' neighbour loads in flight (the one-parity FP32 launches of
+// hop.hip take three instead); four for the packed FP16 path
 // (interleaved layout, Ls = 16: neighbour spinors stay packed, 105-114
 // registers, no spills), three for other 16-bit storage (which spills at
 // four).
