@@ -88,14 +88,16 @@ __device__ inline int member_of(const UnitHdr& h, int u) {
 // g_local). One kernel per form: a kernel holding both bodies runs out of
 // registers.
 // Waves per SIMD the grouped hop's registers are planned for, so that no
-// form spills: FP64 takes one (its permute form needs more than the 256
-// registers two waves leave; FP64 runs only in the reliable updates), the
+// form spills: FP64 two on DPP rows in the interleaved layout (253-256
+// registers) and one otherwise (its permute form needs more than the 256
+// registers two waves leave; FP64 runs only in the reliable updates and in
+// plain FP64 pools), the
 // permute form of 16-bit storage three in the interleaved layout (144-162
 // registers) and two in the split one, FP32 interleaved three (all grouped
 // hops are one-parity ones), the others as the single-context hop.
 template <class S, int LAYOUT, bool DPP16> struct GroupWaves {
   static constexpr int v =
-      sizeof(S) == 8 ? 1
+      sizeof(S) == 8 ? ((DPP16 && LAYOUT == QDWF_RIRI) ? 2 : 1)
       : (sizeof(S) == 2 && !DPP16) ? (LAYOUT == QDWF_RIRI ? 3 : 2)
       : (std::is_same<S, float>::value && LAYOUT == QDWF_RIRI) ? 3
       : WavesPerEU<S, LAYOUT, DPP16>::v;
