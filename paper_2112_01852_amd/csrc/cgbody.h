@@ -129,6 +129,7 @@ __device__ inline void k_alpha_body(const double* __restrict__ part, int NB,
   if (threadIdx.x) return;
   RhsState& s = st[q];
   s.fresh = 0;
+  s.alpha_prev = s.alpha;
   if (s.status != ST_RUN) return;
   s.pAp = pAp;
   if (!(pAp > 0.0) || !isfinite(pAp)) {
@@ -146,6 +147,7 @@ __device__ inline void k_beta_body(const double* __restrict__ part, int NB,
   const double rr_new = part_sum(part, NB, q, sh);
   if (threadIdx.x) return;
   RhsState& s = st[q];
+  s.xstep_prev = s.xstep;
   s.xstep = s.status == ST_RUN;
   if (s.status != ST_RUN) return;
   s.iters += 1;
@@ -207,6 +209,116 @@ __device__ inline void k_update_px_body(SX* __restrict__ x, const SR* __restrict
     const T pv = (T)Store<SP>::to(pr[i]);
     xr[i] = Store<SX>::from((T)Store<SX>::to(xr[i]) + al * pv);
     if (run) pr[i] = Store<SP>::from((T)Store<SR>::to(rr[i]) + be * pv);
+  }
+}
+
+// qdwf_solve pairs its iterations so that x is updated every second one:
+// the search direction alternates between two slots, pa (read by the first
+// iteration of a pair) and pb (by the second).
+// First of a pair: pb = r + beta pa while the rhs keeps running (one that
+// pauses here keeps its direction in pa).
+template <class SR, class SP>
+__device__ inline void k_pair_p_body(const SR* __restrict__ r, const SP* __restrict__ pa,
+                                     SP* __restrict__ pb, long n, long rs,
+                                     const RhsState* __restrict__ st, int vec,
+    int bx, int NB, int q) {
+  typedef typename Store<SR>::compute T;
+  const RhsState& s = st[q];
+  if (s.status != ST_RUN) return;
+  const T be = (T)s.beta;
+  const SR* rr = r + (long)q * rs;
+  const SP* ar = pa + (long)q * rs;
+  SP* br = pb + (long)q * rs;
+  constexpr int E = ChunkWidth<SR, SP>::e;
+  const long nt = vec ? n / TILE : 0;
+  const int lane = threadIdx.x & 63;
+  const long t1 = nt * (bx + 1) / NB;
+  for (long t = nt * bx / NB + (threadIdx.x >> 6); t < t1; t += RT / 64) {
+#pragma unroll
+    for (int j = 0; j < 8 / E; ++j) {
+      const long i = t * TILE + j * 64 * E + lane * E;
+      T rv[E], pv[E];
+      Chunk<SR, E>::ld(rr + i, rv);
+      Chunk<SP, E>::ld(ar + i, pv);
+#pragma unroll
+      for (int k = 0; k < E; ++k) pv[k] = rv[k] + be * pv[k];
+      Chunk<SP, E>::st(br + i, pv);
+    }
+  }
+  for (long i = TILE * nt + (long)bx * RT + threadIdx.x; i < n; i += (long)NB * RT)
+    br[i] = Store<SP>::from((T)Store<SR>::to(rr[i]) + be * (T)Store<SP>::to(ar[i]));
+}
+
+// Second of a pair: x += alpha_prev pa + alpha pb (each term if its
+// iteration took its step), then pa = r + beta pb while the rhs keeps
+// running, or pa = pb if it pauses here (so that its direction is in pa).
+template <class SX, class SR, class SP>
+__device__ inline void k_pair_px_body(SX* __restrict__ x, const SR* __restrict__ r,
+                                      SP* __restrict__ pa, const SP* __restrict__ pb, long n,
+                                      long rs, const RhsState* __restrict__ st, int vec,
+    int bx, int NB, int q) {
+  typedef typename Store<SR>::compute T;
+  const RhsState& s = st[q];
+  const bool s0 = s.xstep_prev, s1 = s.xstep;
+  if (!s0 && !s1) return;
+  const bool run = s.status == ST_RUN;
+  const T a0 = s0 ? (T)s.alpha_prev : (T)0, a1 = s1 ? (T)s.alpha : (T)0, be = (T)s.beta;
+  SX* xr = x + (long)q * rs;
+  const SR* rr = r + (long)q * rs;
+  SP* ar = pa + (long)q * rs;
+  const SP* br = pb + (long)q * rs;
+  constexpr int E = ChunkWidth<SX, SR, SP>::e;
+  const long nt = vec ? n / TILE : 0;
+  const int lane = threadIdx.x & 63;
+  const long t1 = nt * (bx + 1) / NB;
+  for (long t = nt * bx / NB + (threadIdx.x >> 6); t < t1; t += RT / 64) {
+#pragma unroll
+    for (int j = 0; j < 8 / E; ++j) {
+      const long i = t * TILE + j * 64 * E + lane * E;
+      T av[E], bv[E], xv[E];
+      Chunk<SP, E>::ld(ar + i, av);
+      Chunk<SP, E>::ld(br + i, bv);
+      Chunk<SX, E>::ld(xr + i, xv);
+#pragma unroll
+      for (int k = 0; k < E; ++k) xv[k] = (xv[k] + a0 * av[k]) + a1 * bv[k];
+      Chunk<SX, E>::st(xr + i, xv);
+      if (run) {
+        T rv[E];
+        Chunk<SR, E>::ld(rr + i, rv);
+#pragma unroll
+        for (int k = 0; k < E; ++k) av[k] = rv[k] + be * bv[k];
+        Chunk<SP, E>::st(ar + i, av);
+      } else if (s1) {
+        Chunk<SP, E>::st(ar + i, bv);
+      }
+    }
+  }
+  for (long i = TILE * nt + (long)bx * RT + threadIdx.x; i < n; i += (long)NB * RT) {
+    const T av = (T)Store<SP>::to(ar[i]), bv = (T)Store<SP>::to(br[i]);
+    xr[i] = Store<SX>::from(((T)Store<SX>::to(xr[i]) + a0 * av) + a1 * bv);
+    if (run) ar[i] = Store<SP>::from((T)Store<SR>::to(rr[i]) + be * bv);
+    else if (s1) ar[i] = br[i];
+  }
+}
+
+// After a run of iterations that ends on the first of a pair: x += alpha pa
+// if that iteration took its step, and pa = pb while the rhs keeps running.
+template <class SX, class SP>
+__device__ inline void k_pair_flush_body(SX* __restrict__ x, SP* __restrict__ pa,
+                                         const SP* __restrict__ pb, long n, long rs,
+                                         const RhsState* __restrict__ st,
+    int bx, int NB, int q) {
+  typedef typename Store<SX>::compute T;
+  const RhsState& s = st[q];
+  const bool s1 = s.xstep, run = s.status == ST_RUN;
+  if (!s1 && !run) return;
+  const T a1 = s1 ? (T)s.alpha : (T)0;
+  SX* xr = x + (long)q * rs;
+  SP* ar = pa + (long)q * rs;
+  const SP* br = pb + (long)q * rs;
+  for (long i = (long)bx * RT + threadIdx.x; i < n; i += (long)NB * RT) {
+    xr[i] = Store<SX>::from((T)Store<SX>::to(xr[i]) + a1 * (T)Store<SP>::to(ar[i]));
+    if (run) ar[i] = br[i];
   }
 }
 

@@ -54,11 +54,25 @@ __global__ void __launch_bounds__(RT) k_beta(const double* __restrict__ part, in
   k_beta_body(part, NB, st, delta2, blockIdx.x, sh);
 }
 
+template <class SR, class SP>
+__global__ void __launch_bounds__(RT) k_pair_p(const SR* __restrict__ r, const SP* __restrict__ pa,
+                                               SP* __restrict__ pb, long n,
+                                               const RhsState* __restrict__ st, int vec) {
+  k_pair_p_body<SR, SP>(r, pa, pb, n, n, st, vec, blockIdx.x, gridDim.x, blockIdx.y);
+}
+
 template <class SX, class SR, class SP>
-__global__ void __launch_bounds__(RT) k_update_px(SX* __restrict__ x, const SR* __restrict__ r,
-                                                  SP* __restrict__ p, long n,
-                                                  const RhsState* __restrict__ st, int vec) {
-  k_update_px_body<SX, SR, SP>(x, r, p, n, n, st, vec, blockIdx.x, gridDim.x, blockIdx.y);
+__global__ void __launch_bounds__(RT) k_pair_px(SX* __restrict__ x, const SR* __restrict__ r,
+                                                SP* __restrict__ pa, const SP* __restrict__ pb,
+                                                long n, const RhsState* __restrict__ st, int vec) {
+  k_pair_px_body<SX, SR, SP>(x, r, pa, pb, n, n, st, vec, blockIdx.x, gridDim.x, blockIdx.y);
+}
+
+template <class SX, class SP>
+__global__ void __launch_bounds__(RT) k_pair_flush(SX* __restrict__ x, SP* __restrict__ pa,
+                                                   const SP* __restrict__ pb, long n,
+                                                   const RhsState* __restrict__ st) {
+  k_pair_flush_body<SX, SP>(x, pa, pb, n, n, st, blockIdx.x, gridDim.x, blockIdx.y);
 }
 
 __global__ void __launch_bounds__(RT) k_sum_sites(const double* __restrict__ v, long n,
@@ -325,7 +339,7 @@ size_t dot_ws_bytes(long n, int nrhs) {
 
 // ---- the solver ----------------------------------------------------------------
 
-Layout solver_layout(long n, int nrhs, int inner) {
+Layout solver_layout(long n, int nrhs, int inner, bool pair) {
   Layout L;
   const size_t sS = prec_bytes(inner);
   const size_t sR = inner == QDWF_F64 ? 8 : 4;
@@ -350,6 +364,8 @@ Layout solver_layout(long n, int nrhs, int inner) {
   L.off_part = o; o += al256(sizeof(double) * ((size_t)reduce_blocks(2 * n) * nrhs + 2 * (size_t)nrhs));
   L.off_state = o; o += al256(sizeof(RhsState) * (size_t)nrhs);
   L.off_stage = o; o += al256(8 * (size_t)n * nrhs * 2);   // FULL: source prep / rhs
+  L.off_p2 = 0;
+  if (pair) { L.off_p2 = o; o += vS; }
   L.total = o;
   return L;
 }
@@ -384,12 +400,19 @@ struct Cg {
   //   alpha = |r|^2 / |v|^2;
   //   r -= alpha M_pc^dag v inside the last hop (Ap is never stored), with
   //   |r|^2 summed there;
-  //   beta; x += alpha p and p = r + beta p in one pass.
+  //   beta; p = r + beta p, and x += alpha p every second iteration.
   // The hops leave one sum per checkerboard site (in the room of Ap), which
   // k_sum_sites reduces with a block count that depends only on the field size.
-  int inner_iteration() {
+  // Iterations come in pairs (j = 0, 1 within a run of iterations): the
+  // first reads p from slot a and writes the next p to slot b; the second
+  // reads slot b, adds both iterations' steps to x in one pass and writes
+  // the next p to slot a. A run that ends on the first of a pair is closed
+  // by pair_flush, so every run starts from slot a.
+  int inner_iteration(int j) {
     int rc;
-    S* p = at<S>(L.off_p);
+    S* pa = at<S>(L.off_p);
+    S* pb = at<S>(L.off_p2);
+    S* p = (j & 1) ? pb : pa;
     S* v = at<S>(L.off_v);
     R* x = at<R>(L.off_xl);
     RR* r = at<RR>(L.off_rl);
@@ -397,7 +420,7 @@ struct Cg {
     const long nsite = ctx->g.Vh;
     const int NBs = site_blocks(nsite);
     // the workspace arrays start on 256-byte boundaries and n is a multiple of 24
-    const int vec = vec_ok<S>(n, {p}) && vec_ok<R>(n, {x}) && vec_ok<RR>(n, {r}) ? 1 : 0;
+    const int vec = vec_ok<S>(n, {pa, pb}) && vec_ok<R>(n, {x}) && vec_ok<RR>(n, {r}) ? 1 : 0;
     // the hops of a right-hand side that is not running do no work
     static_assert(sizeof(RhsState) % sizeof(double) == 0, "RhsState is read as ints and doubles");
     const int* skip = reinterpret_cast<const int*>(
@@ -417,9 +440,24 @@ struct Cg {
       return rc;
     hipLaunchKernelGGL(k_sum_sites, dim3(NBs, nrhs), dim3(RT), 0, st, site, nsite, part());
     hipLaunchKernelGGL(k_beta, dim3(nrhs), dim3(RT), 0, st, part(), NBs, d_state, delta2);
-    hipLaunchKernelGGL((k_update_px<R, RR, S>), grid(), dim3(RT), 0, st, x, r, p, n, d_state, vec);
+    if (j & 1)
+      hipLaunchKernelGGL((k_pair_px<R, RR, S>), grid(), dim3(RT), 0, st, x, r, pa, pb, n, d_state,
+                         vec);
+    else
+      hipLaunchKernelGGL((k_pair_p<RR, S>), grid(), dim3(RT), 0, st, r, pa, pb, n, d_state, vec);
     QDWF_HIP(hipGetLastError());
     hop_applications += 4;
+    return QDWF_OK;
+  }
+
+  // count iterations, closed so that x holds every step and p is in slot a
+  int inner_run(int count) {
+    int rc = 0;
+    for (int i = 0; i < count && !rc; ++i) rc = inner_iteration(i);
+    if (rc || !(count & 1)) return rc;
+    hipLaunchKernelGGL((k_pair_flush<R, S>), grid(), dim3(RT), 0, st, at<R>(L.off_xl), at<S>(L.off_p),
+                       at<S>(L.off_p2), n, d_state);
+    QDWF_HIP(hipGetLastError());
     return QDWF_OK;
   }
 
@@ -544,7 +582,7 @@ struct Cg {
         forget_graph(ctx);
         QDWF_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
         const int64_t h0 = hop_applications;
-        for (int i = 0; i < k && !rc; ++i) rc = inner_iteration();
+        rc = inner_run(k);
         hop_applications = h0;
         hipGraph_t graph = nullptr;
         const hipError_t e = hipStreamEndCapture(st, &graph);
@@ -570,7 +608,7 @@ struct Cg {
       hop_applications += 4 * k;
     } else {
       rc = 0;
-      for (int i = 0; i < batch && !rc; ++i) rc = inner_iteration();
+      rc = inner_run(batch);
       if (rc) return rc;
     }
     return fetch_async();
@@ -632,7 +670,7 @@ int axpby64(double* out, const double* a, double ca, const double* b, double cb,
 
 size_t solve_ws_bytes(const qdwf_ctx* ctx, int inner, int nrhs, int system) {
   const long n = ctx->g.n5h * 24;
-  size_t b = solver_layout(n, nrhs, inner).total;
+  size_t b = solver_layout(n, nrhs, inner, true).total;
   (void)system;
   return b;
 }
@@ -654,7 +692,7 @@ static int solve_normal(qdwf_ctx* ctx, double* x, const double* b, int nrhs,
     cg.n = n;
     cg.NB = reduce_blocks(n);
     cg.ws = reinterpret_cast<char*>(ws);
-    cg.L = solver_layout(n, nrhs, prm.inner_prec);
+    cg.L = solver_layout(n, nrhs, prm.inner_prec, true);
     cg.xh = x;
     cg.rs_x = n;
     cg.b = b;
@@ -683,7 +721,7 @@ static int solve_full(qdwf_ctx* ctx, double* x, const double* b, int nrhs,
                       const qdwf_solve_params& prm, qdwf_solve_stats* stats, void* ws,
                       hipStream_t st) {
   const long n = ctx->g.n5h * 24;
-  const Layout L = solver_layout(n, nrhs, prm.inner_prec);
+  const Layout L = solver_layout(n, nrhs, prm.inner_prec, true);
   char* w = reinterpret_cast<char*>(ws);
   // FP64 scratch borrowed from the solver layout before the solve starts and
   // after it ends: rh, ax, vh, t1h, t2h, plus the two staging vectors.
