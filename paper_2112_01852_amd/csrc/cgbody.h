@@ -121,15 +121,15 @@ __device__ inline void k_dot_body(const SA* __restrict__ a, const SB* __restrict
   if (threadIdx.x == 0) part[(long)r * NB + bx] = t;
 }
 
-// alpha = rr / <p, Ap>, <p, Ap> = |M_pc p|^2 from the partials
+// alpha = rr / <p, Ap>, <p, Ap> = |M_pc p|^2 from the partials; j >= 0:
+// also kept as alpha_hist[j] (iteration j of a group of qdwf_solve)
 __device__ inline void k_alpha_body(const double* __restrict__ part, int NB,
                                               RhsState* __restrict__ st,
-    int q, double* sh) {
+    int q, double* sh, int j = -1) {
   const double pAp = part_sum(part, NB, q, sh);
   if (threadIdx.x) return;
   RhsState& s = st[q];
   s.fresh = 0;
-  s.alpha_prev = s.alpha;
   if (s.status != ST_RUN) return;
   s.pAp = pAp;
   if (!(pAp > 0.0) || !isfinite(pAp)) {
@@ -138,17 +138,18 @@ __device__ inline void k_alpha_body(const double* __restrict__ part, int NB,
     return;
   }
   s.alpha = s.rr / pAp;
+  if (j >= 0) s.alpha_hist[j] = s.alpha;
 }
 
 // beta = rr_new / rr ; decide whether a reliable update is due
 __device__ inline void k_beta_body(const double* __restrict__ part, int NB,
                                              RhsState* __restrict__ st, double delta2,
-    int q, double* sh) {
+    int q, double* sh, int j = -1) {
   const double rr_new = part_sum(part, NB, q, sh);
   if (threadIdx.x) return;
   RhsState& s = st[q];
-  s.xstep_prev = s.xstep;
   s.xstep = s.status == ST_RUN;
+  if (j >= 0) s.xmask = (j == 0 ? 0 : s.xmask) | (s.xstep << j);
   if (s.status != ST_RUN) return;
   s.iters += 1;
   if (!isfinite(rr_new)) {
@@ -212,31 +213,32 @@ __device__ inline void k_update_px_body(SX* __restrict__ x, const SR* __restrict
   }
 }
 
-// qdwf_solve pairs its iterations so that x is updated every second one:
-// the search direction alternates between two slots, pa (read by the first
-// iteration of a pair) and pb (by the second).
-// First of a pair: pb = r + beta pa while the rhs keeps running (one that
-// pauses here keeps its direction in pa).
+// qdwf_solve runs its iterations in groups of up to kGroupSlots and updates
+// x once per group: iteration j of a group reads its search direction from
+// slot j (slot stride ps reals) and writes the next one to slot j + 1; the
+// last adds every step of the group to x and writes the next direction to
+// slot 0, where the next group (and a reliable update) starts.
+// Iteration j < last: slot j+1 = r + beta slot j while the rhs keeps running
+// (one that pauses here keeps its direction in slot j).
 template <class SR, class SP>
-__device__ inline void k_pair_p_body(const SR* __restrict__ r, const SP* __restrict__ pa,
-                                     SP* __restrict__ pb, long n, long rs,
-                                     const RhsState* __restrict__ st, int vec,
+__device__ inline void k_grp_p_body(const SR* __restrict__ r, SP* __restrict__ p0, long ps, int j,
+                                    long n, long rs, const RhsState* __restrict__ st, int vec,
     int bx, int NB, int q) {
   typedef typename Store<SR>::compute T;
   const RhsState& s = st[q];
   if (s.status != ST_RUN) return;
   const T be = (T)s.beta;
   const SR* rr = r + (long)q * rs;
-  const SP* ar = pa + (long)q * rs;
-  SP* br = pb + (long)q * rs;
+  const SP* ar = p0 + (long)j * ps + (long)q * rs;
+  SP* br = p0 + (long)(j + 1) * ps + (long)q * rs;
   constexpr int E = ChunkWidth<SR, SP>::e;
   const long nt = vec ? n / TILE : 0;
   const int lane = threadIdx.x & 63;
   const long t1 = nt * (bx + 1) / NB;
   for (long t = nt * bx / NB + (threadIdx.x >> 6); t < t1; t += RT / 64) {
 #pragma unroll
-    for (int j = 0; j < 8 / E; ++j) {
-      const long i = t * TILE + j * 64 * E + lane * E;
+    for (int jj = 0; jj < 8 / E; ++jj) {
+      const long i = t * TILE + jj * 64 * E + lane * E;
       T rv[E], pv[E];
       Chunk<SR, E>::ld(rr + i, rv);
       Chunk<SP, E>::ld(ar + i, pv);
@@ -249,76 +251,70 @@ __device__ inline void k_pair_p_body(const SR* __restrict__ r, const SP* __restr
     br[i] = Store<SP>::from((T)Store<SR>::to(rr[i]) + be * (T)Store<SP>::to(ar[i]));
 }
 
-// Second of a pair: x += alpha_prev pa + alpha pb (each term if its
-// iteration took its step), then pa = r + beta pb while the rhs keeps
-// running, or pa = pb if it pauses here (so that its direction is in pa).
+// Last iteration of a group of len: x += alpha_hist[i] slot i for every
+// iteration i that took its step, in order (the rounding of one update per
+// iteration); then slot 0 = r + beta slot len-1 while the rhs keeps running,
+// or slot 0 = slot m if it paused after its last step m > 0.
 template <class SX, class SR, class SP>
-__device__ inline void k_pair_px_body(SX* __restrict__ x, const SR* __restrict__ r,
-                                      SP* __restrict__ pa, const SP* __restrict__ pb, long n,
-                                      long rs, const RhsState* __restrict__ st, int vec,
+__device__ inline void k_grp_last_body(SX* __restrict__ x, const SR* __restrict__ r,
+                                       SP* __restrict__ p0, long ps, int len, long n, long rs,
+                                       const RhsState* __restrict__ st, int vec,
     int bx, int NB, int q) {
   typedef typename Store<SR>::compute T;
   const RhsState& s = st[q];
-  const bool s0 = s.xstep_prev, s1 = s.xstep;
-  if (!s0 && !s1) return;
+  const int mask = s.xmask & ((1 << len) - 1);
   const bool run = s.status == ST_RUN;
-  const T a0 = s0 ? (T)s.alpha_prev : (T)0, a1 = s1 ? (T)s.alpha : (T)0, be = (T)s.beta;
+  if (!mask && !run) return;
+  int m = 0;   // last iteration that took its step
+  for (int i = 0; i < len; ++i)
+    if (mask >> i & 1) m = i;
+  T al[kGroupSlots];
+#pragma unroll
+  for (int i = 0; i < kGroupSlots; ++i) al[i] = (T)s.alpha_hist[i];
+  const T be = (T)s.beta;
   SX* xr = x + (long)q * rs;
   const SR* rr = r + (long)q * rs;
-  SP* ar = pa + (long)q * rs;
-  const SP* br = pb + (long)q * rs;
+  SP* pr = p0 + (long)q * rs;
+  const SP* lastp = pr + (long)(run ? len - 1 : m) * ps;
+  const bool copy = run || m > 0;
   constexpr int E = ChunkWidth<SX, SR, SP>::e;
   const long nt = vec ? n / TILE : 0;
   const int lane = threadIdx.x & 63;
   const long t1 = nt * (bx + 1) / NB;
   for (long t = nt * bx / NB + (threadIdx.x >> 6); t < t1; t += RT / 64) {
 #pragma unroll
-    for (int j = 0; j < 8 / E; ++j) {
-      const long i = t * TILE + j * 64 * E + lane * E;
-      T av[E], bv[E], xv[E];
-      Chunk<SP, E>::ld(ar + i, av);
-      Chunk<SP, E>::ld(br + i, bv);
+    for (int jj = 0; jj < 8 / E; ++jj) {
+      const long i = t * TILE + jj * 64 * E + lane * E;
+      T xv[E], pv[E];
       Chunk<SX, E>::ld(xr + i, xv);
+      for (int g = 0; g < len; ++g) {
+        if (!(mask >> g & 1)) continue;
+        Chunk<SP, E>::ld(pr + (long)g * ps + i, pv);
 #pragma unroll
-      for (int k = 0; k < E; ++k) xv[k] = (xv[k] + a0 * av[k]) + a1 * bv[k];
+        for (int k = 0; k < E; ++k) xv[k] = xv[k] + al[g] * pv[k];
+      }
       Chunk<SX, E>::st(xr + i, xv);
-      if (run) {
-        T rv[E];
-        Chunk<SR, E>::ld(rr + i, rv);
+      if (copy) {
+        Chunk<SP, E>::ld(lastp + i, pv);
+        if (run) {
+          T rv[E];
+          Chunk<SR, E>::ld(rr + i, rv);
 #pragma unroll
-        for (int k = 0; k < E; ++k) av[k] = rv[k] + be * bv[k];
-        Chunk<SP, E>::st(ar + i, av);
-      } else if (s1) {
-        Chunk<SP, E>::st(ar + i, bv);
+          for (int k = 0; k < E; ++k) pv[k] = rv[k] + be * pv[k];
+        }
+        Chunk<SP, E>::st(pr + i, pv);
       }
     }
   }
   for (long i = TILE * nt + (long)bx * RT + threadIdx.x; i < n; i += (long)NB * RT) {
-    const T av = (T)Store<SP>::to(ar[i]), bv = (T)Store<SP>::to(br[i]);
-    xr[i] = Store<SX>::from(((T)Store<SX>::to(xr[i]) + a0 * av) + a1 * bv);
-    if (run) ar[i] = Store<SP>::from((T)Store<SR>::to(rr[i]) + be * bv);
-    else if (s1) ar[i] = br[i];
-  }
-}
-
-// After a run of iterations that ends on the first of a pair: x += alpha pa
-// if that iteration took its step, and pa = pb while the rhs keeps running.
-template <class SX, class SP>
-__device__ inline void k_pair_flush_body(SX* __restrict__ x, SP* __restrict__ pa,
-                                         const SP* __restrict__ pb, long n, long rs,
-                                         const RhsState* __restrict__ st,
-    int bx, int NB, int q) {
-  typedef typename Store<SX>::compute T;
-  const RhsState& s = st[q];
-  const bool s1 = s.xstep, run = s.status == ST_RUN;
-  if (!s1 && !run) return;
-  const T a1 = s1 ? (T)s.alpha : (T)0;
-  SX* xr = x + (long)q * rs;
-  SP* ar = pa + (long)q * rs;
-  const SP* br = pb + (long)q * rs;
-  for (long i = (long)bx * RT + threadIdx.x; i < n; i += (long)NB * RT) {
-    xr[i] = Store<SX>::from((T)Store<SX>::to(xr[i]) + a1 * (T)Store<SP>::to(ar[i]));
-    if (run) ar[i] = br[i];
+    T xv = (T)Store<SX>::to(xr[i]);
+    for (int g = 0; g < len; ++g)
+      if (mask >> g & 1) xv = xv + al[g] * (T)Store<SP>::to(pr[(long)g * ps + i]);
+    xr[i] = Store<SX>::from(xv);
+    if (copy) {
+      const T pv = (T)Store<SP>::to(lastp[i]);
+      pr[i] = Store<SP>::from(run ? (T)Store<SR>::to(rr[i]) + be * pv : pv);
+    }
   }
 }
 

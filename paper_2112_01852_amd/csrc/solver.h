@@ -12,7 +12,7 @@ struct RhsState {
   double rr;           // inner |r|^2 in scaled units
   double rr_prev;      // inner |r|^2 of the previous iteration
   double pAp, alpha, beta;
-  double alpha_prev;   // alpha of the iteration before (paired x updates)
+  double alpha_hist[8];   // alpha of each iteration of the current group (grouped x updates)
   double rr_ru;        // inner |r|^2 right after the last reliable update
   double sigma;        // scale of the inner vectors (physical = inner / sigma)
   double sigma_ratio;  // new sigma / old sigma at a reliable update
@@ -26,7 +26,7 @@ struct RhsState {
   int final;           // out of iterations: the next reliable update ends the solve
   int max_iter;        // iteration limit kept on the device (0: the host enforces it)
   int xstep;           // the iteration's x step is due (running when |r|^2 was taken)
-  int xstep_prev;      // xstep of the iteration before (paired x updates)
+  int xmask;           // bit j: iteration j of the current group took its step
 };
 
 // The CG step a solver iteration fuses into the epilogue hop of M_pc or
@@ -49,12 +49,14 @@ struct Layout {
   // inner: x_lo, r_lo (R type); p, Ap, v, te1, te2 (S type)
   size_t off_xl, off_rl, off_p, off_ap, off_v, off_t1, off_t2;
   size_t off_part, off_state, off_stage;
-  size_t off_p2;   // qdwf_solve's second search-direction slot (paired iterations), or 0
   size_t total;
 };
-// pair: with the second search-direction slot of qdwf_solve's paired
-// iterations (the serving pool's members have none)
-Layout solver_layout(long n, int nrhs, int inner, bool pair = false);
+// Search-direction slots of qdwf_solve's grouped iterations (the serving
+// pool's members have one).
+constexpr int kGroupSlots = 8;
+// grouped: off_p is the first of kGroupSlots consecutive slots, each
+// al256(p bytes) apart
+Layout solver_layout(long n, int nrhs, int inner, bool grouped = false);
 
 int reduce_blocks(long n);
 int site_blocks(long nsite);

@@ -43,36 +43,29 @@ __global__ void __launch_bounds__(RT) k_dot(const SA* __restrict__ a, const SB* 
 }
 
 __global__ void __launch_bounds__(RT) k_alpha(const double* __restrict__ part, int NB,
-                                              RhsState* __restrict__ st) {
+                                              RhsState* __restrict__ st, int j) {
   __shared__ double sh[RT];
-  k_alpha_body(part, NB, st, blockIdx.x, sh);
+  k_alpha_body(part, NB, st, blockIdx.x, sh, j);
 }
 
 __global__ void __launch_bounds__(RT) k_beta(const double* __restrict__ part, int NB,
-                                             RhsState* __restrict__ st, double delta2) {
+                                             RhsState* __restrict__ st, double delta2, int j) {
   __shared__ double sh[RT];
-  k_beta_body(part, NB, st, delta2, blockIdx.x, sh);
+  k_beta_body(part, NB, st, delta2, blockIdx.x, sh, j);
 }
 
 template <class SR, class SP>
-__global__ void __launch_bounds__(RT) k_pair_p(const SR* __restrict__ r, const SP* __restrict__ pa,
-                                               SP* __restrict__ pb, long n,
-                                               const RhsState* __restrict__ st, int vec) {
-  k_pair_p_body<SR, SP>(r, pa, pb, n, n, st, vec, blockIdx.x, gridDim.x, blockIdx.y);
+__global__ void __launch_bounds__(RT) k_grp_p(const SR* __restrict__ r, SP* __restrict__ p0, long ps,
+                                              int j, long n, const RhsState* __restrict__ st,
+                                              int vec) {
+  k_grp_p_body<SR, SP>(r, p0, ps, j, n, n, st, vec, blockIdx.x, gridDim.x, blockIdx.y);
 }
 
 template <class SX, class SR, class SP>
-__global__ void __launch_bounds__(RT) k_pair_px(SX* __restrict__ x, const SR* __restrict__ r,
-                                                SP* __restrict__ pa, const SP* __restrict__ pb,
-                                                long n, const RhsState* __restrict__ st, int vec) {
-  k_pair_px_body<SX, SR, SP>(x, r, pa, pb, n, n, st, vec, blockIdx.x, gridDim.x, blockIdx.y);
-}
-
-template <class SX, class SP>
-__global__ void __launch_bounds__(RT) k_pair_flush(SX* __restrict__ x, SP* __restrict__ pa,
-                                                   const SP* __restrict__ pb, long n,
-                                                   const RhsState* __restrict__ st) {
-  k_pair_flush_body<SX, SP>(x, pa, pb, n, n, st, blockIdx.x, gridDim.x, blockIdx.y);
+__global__ void __launch_bounds__(RT) k_grp_last(SX* __restrict__ x, const SR* __restrict__ r,
+                                                 SP* __restrict__ p0, long ps, int len, long n,
+                                                 const RhsState* __restrict__ st, int vec) {
+  k_grp_last_body<SX, SR, SP>(x, r, p0, ps, len, n, n, st, vec, blockIdx.x, gridDim.x, blockIdx.y);
 }
 
 __global__ void __launch_bounds__(RT) k_sum_sites(const double* __restrict__ v, long n,
@@ -339,7 +332,7 @@ size_t dot_ws_bytes(long n, int nrhs) {
 
 // ---- the solver ----------------------------------------------------------------
 
-Layout solver_layout(long n, int nrhs, int inner, bool pair) {
+Layout solver_layout(long n, int nrhs, int inner, bool grouped) {
   Layout L;
   const size_t sS = prec_bytes(inner);
   const size_t sR = inner == QDWF_F64 ? 8 : 4;
@@ -355,7 +348,7 @@ Layout solver_layout(long n, int nrhs, int inner, bool pair) {
   L.off_t2h = o; o += v64;
   L.off_xl = o; o += vR;
   L.off_rl = o; o += al256(sRl * (size_t)n * nrhs);
-  L.off_p = o; o += vS;
+  L.off_p = o; o += vS * (grouped ? kGroupSlots : 1);
   L.off_ap = o; o += vS;
   L.off_v = o; o += vS;
   L.off_t1 = o; o += vS;
@@ -364,8 +357,6 @@ Layout solver_layout(long n, int nrhs, int inner, bool pair) {
   L.off_part = o; o += al256(sizeof(double) * ((size_t)reduce_blocks(2 * n) * nrhs + 2 * (size_t)nrhs));
   L.off_state = o; o += al256(sizeof(RhsState) * (size_t)nrhs);
   L.off_stage = o; o += al256(8 * (size_t)n * nrhs * 2);   // FULL: source prep / rhs
-  L.off_p2 = 0;
-  if (pair) { L.off_p2 = o; o += vS; }
   L.total = o;
   return L;
 }
@@ -400,19 +391,18 @@ struct Cg {
   //   alpha = |r|^2 / |v|^2;
   //   r -= alpha M_pc^dag v inside the last hop (Ap is never stored), with
   //   |r|^2 summed there;
-  //   beta; p = r + beta p, and x += alpha p every second iteration.
+  //   beta; p = r + beta p, and x += alpha p once per group of iterations.
   // The hops leave one sum per checkerboard site (in the room of Ap), which
   // k_sum_sites reduces with a block count that depends only on the field size.
-  // Iterations come in pairs (j = 0, 1 within a run of iterations): the
-  // first reads p from slot a and writes the next p to slot b; the second
-  // reads slot b, adds both iterations' steps to x in one pass and writes
-  // the next p to slot a. A run that ends on the first of a pair is closed
-  // by pair_flush, so every run starts from slot a.
-  int inner_iteration(int j) {
+  // Iterations come in groups of up to kGroupSlots (iteration j of a group
+  // of len): iteration j reads p from slot j and writes the next p to slot
+  // j + 1; the last one adds every step of the group to x in one pass and
+  // writes the next p to slot 0, where every group starts.
+  int inner_iteration(int j, int len) {
     int rc;
-    S* pa = at<S>(L.off_p);
-    S* pb = at<S>(L.off_p2);
-    S* p = (j & 1) ? pb : pa;
+    S* p0 = at<S>(L.off_p);
+    const long ps = (long)(al256(prec_bytes(inner) * (size_t)n * nrhs) / prec_bytes(inner));
+    S* p = p0 + (long)j * ps;
     S* v = at<S>(L.off_v);
     R* x = at<R>(L.off_xl);
     RR* r = at<RR>(L.off_rl);
@@ -420,7 +410,7 @@ struct Cg {
     const long nsite = ctx->g.Vh;
     const int NBs = site_blocks(nsite);
     // the workspace arrays start on 256-byte boundaries and n is a multiple of 24
-    const int vec = vec_ok<S>(n, {pa, pb}) && vec_ok<R>(n, {x}) && vec_ok<RR>(n, {r}) ? 1 : 0;
+    const int vec = vec_ok<S>(n, {p0}) && vec_ok<R>(n, {x}) && vec_ok<RR>(n, {r}) ? 1 : 0;
     // the hops of a right-hand side that is not running do no work
     static_assert(sizeof(RhsState) % sizeof(double) == 0, "RhsState is read as ints and doubles");
     const int* skip = reinterpret_cast<const int*>(
@@ -431,7 +421,7 @@ struct Cg {
                         skip, sk, &f1)))
       return rc;
     hipLaunchKernelGGL(k_sum_sites, dim3(NBs, nrhs), dim3(RT), 0, st, site, nsite, part());
-    hipLaunchKernelGGL(k_alpha, dim3(nrhs), dim3(RT), 0, st, part(), NBs, d_state);
+    hipLaunchKernelGGL(k_alpha, dim3(nrhs), dim3(RT), 0, st, part(), NBs, d_state, j);
     const double* alpha = reinterpret_cast<const double*>(
         reinterpret_cast<const char*>(d_state) + offsetof(RhsState, alpha));
     CgFuse f2 = {2, r, alpha, (int)(sizeof(RhsState) / sizeof(double)), site};
@@ -439,26 +429,26 @@ struct Cg {
                         nrhs, n, st, skip, sk, &f2)))
       return rc;
     hipLaunchKernelGGL(k_sum_sites, dim3(NBs, nrhs), dim3(RT), 0, st, site, nsite, part());
-    hipLaunchKernelGGL(k_beta, dim3(nrhs), dim3(RT), 0, st, part(), NBs, d_state, delta2);
-    if (j & 1)
-      hipLaunchKernelGGL((k_pair_px<R, RR, S>), grid(), dim3(RT), 0, st, x, r, pa, pb, n, d_state,
-                         vec);
+    hipLaunchKernelGGL(k_beta, dim3(nrhs), dim3(RT), 0, st, part(), NBs, d_state, delta2, j);
+    if (j + 1 < len)
+      hipLaunchKernelGGL((k_grp_p<RR, S>), grid(), dim3(RT), 0, st, r, p0, ps, j, n, d_state, vec);
     else
-      hipLaunchKernelGGL((k_pair_p<RR, S>), grid(), dim3(RT), 0, st, r, pa, pb, n, d_state, vec);
+      hipLaunchKernelGGL((k_grp_last<R, RR, S>), grid(), dim3(RT), 0, st, x, r, p0, ps, len, n,
+                         d_state, vec);
     QDWF_HIP(hipGetLastError());
     hop_applications += 4;
     return QDWF_OK;
   }
 
-  // count iterations, closed so that x holds every step and p is in slot a
+  // count iterations in groups of up to kGroupSlots: after them x holds
+  // every step and the next direction is in slot 0
   int inner_run(int count) {
     int rc = 0;
-    for (int i = 0; i < count && !rc; ++i) rc = inner_iteration(i);
-    if (rc || !(count & 1)) return rc;
-    hipLaunchKernelGGL((k_pair_flush<R, S>), grid(), dim3(RT), 0, st, at<R>(L.off_xl), at<S>(L.off_p),
-                       at<S>(L.off_p2), n, d_state);
-    QDWF_HIP(hipGetLastError());
-    return QDWF_OK;
+    for (int g = 0; g < count && !rc; g += kGroupSlots) {
+      const int len = std::min(kGroupSlots, count - g);
+      for (int j = 0; j < len && !rc; ++j) rc = inner_iteration(j, len);
+    }
+    return rc;
   }
 
   // FP64 true residual and restart of the inner recursion (first: initial setup)
