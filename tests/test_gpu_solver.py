@@ -134,6 +134,46 @@ def test_not_converged_and_nan_are_reported(setup):
 
 
 @pytest.mark.parametrize("inner", [0, 2])
+def test_solve_bitwise_same_for_any_round_length(setup, inner):
+    """x takes the steps of up to eight iterations in one pass, and a group
+    of iterations never spans two rounds of check_every: rounds of 1, 3, 8
+    and 13 iterations (groups cut at every length from 1 to 8), replayed
+    from graphs or launched eagerly, must take the same iterations and
+    reliable updates and give bitwise the same solution."""
+    q, a, U, b, x_ref, D = setup
+    runs = [_solve(q, D, b, inner, use_graph=g, check_every=ce)
+            for ce, g in ((1, 0), (3, 1), (8, 1), (13, 1), (13, 0))]
+    rc0, st0, x0 = runs[0]
+    assert rc0 == q.QDWF_OK, q.qdwf_last_error()
+    for rc, st, x in runs[1:]:
+        assert rc == q.QDWF_OK
+        assert (st.iterations, st.reliable_updates) == (st0.iterations, st0.reliable_updates)
+        assert np.array_equal(x, x0)
+    assert _rel(x0, x_ref) <= 1e-8
+
+
+@pytest.mark.parametrize("check_every", [1, 8, 13])
+@pytest.mark.parametrize("inner", [0, 2])
+def test_max_iter_not_whole_groups(setup, inner, check_every):
+    """A solve stopped by max_iter = 11, a whole number neither of groups of
+    iterations nor of rounds, holds exactly 11 CG steps: in FP64 its x is the
+    oracle's CG stopped after 11 iterations, and the reported true residual
+    is that of the returned x."""
+    q, a, U, b, x_ref, D = setup
+    rc, st, x = _solve(q, D, b, inner, max_iter=11, check_every=check_every)
+    assert rc == q.QDWF_ENOTCONV
+    assert st.iterations == 11
+    if inner == 0:
+        x11, it, res11 = cpu.cg(a, U, b, tol=1e-30, max_iter=11)
+        assert it == 11
+        assert _rel(x, x11) <= 1e-10
+    r = b - cpu.mpc(a, U, cpu.mpc(a, U, x), dagger=True)
+    res = np.linalg.norm(r) / np.linalg.norm(b)
+    assert res > 1e-10
+    assert abs(res - st.true_residual) <= 1e-6 * res
+
+
+@pytest.mark.parametrize("inner", [0, 2])
 def test_fused_cg_step_independent_of_hop_shape(q, tmp_path, inner):
     """The hops carry the CG step's sums as one value per checkerboard site,
     so the solve must be bitwise the same for every launch shape of the hop:
