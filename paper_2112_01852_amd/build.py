@@ -23,11 +23,13 @@ ARCH = os.environ.get("QDWF_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["api.cpp", "hop.hip", "pack.hip", "local.hip", "solver.hip", "tune.cpp", "pool.cpp", "wilson.hip", "stream.hip", "halo.hip", "sweep.hip", "noalloc.hip", "group.hip"]
 
 # Packed-FP32 instructions are switched off for all device code. The
-# two-operand v_dot2c_f32_f16 form is switched off too: it accumulates into
-# its destination, so every product chain that starts from zero cost a
-# register clear; the three-operand v_dot2_f32_f16 takes the zero inline.
+# two-operand v_dot2c_f32_f16 and v_dot2c_f32_bf16 forms are switched off
+# too: they accumulate into their destination, so every product chain that
+# starts from zero cost a register clear; the three-operand v_dot2_f32_f16
+# and v_dot2_f32_bf16 take the zero inline.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                "-Xclang", "-target-feature", "-Xclang", "-dot5-insts"]
+                "-Xclang", "-target-feature", "-Xclang", "-dot5-insts",
+                "-Xclang", "-target-feature", "-Xclang", "-dot13-insts"]
 
 
 def hipcc() -> str:

@@ -64,6 +64,19 @@ template <class S, int LAYOUT = QDWF_RRII, bool DPP16 = false> struct WavesPerEU
       sizeof(S) >= 4 ? 2 : (std::is_same<S, _Float16>::value && LAYOUT == QDWF_RIRI && DPP16) ? 4 : 3;
 };
 
+// The 18 words of a link staged in LDS in its two sign-adjusted forms
+// (link_words), read as four 16-byte and one 8-byte LDS loads.
+__device__ inline void load_link_words(const float* p, uint32_t* U) {
+  const uint4* q4 = reinterpret_cast<const uint4*>(p);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint4 t4 = q4[j];
+    U[4 * j] = t4.x; U[4 * j + 1] = t4.y; U[4 * j + 2] = t4.z; U[4 * j + 3] = t4.w;
+  }
+  const uint2 t2 = reinterpret_cast<const uint2*>(p)[8];
+  U[16] = t2.x; U[17] = t2.y;
+}
+
 // One block's share of a hop launch: logical block L of the launch described
 // by k (its sites, parity and right-hand sides), with smem the block's LDS
 // (the LDS bytes make_hopk reports). Every 5D site's result depends only on
@@ -74,12 +87,17 @@ template <class S, int LAYOUT = QDWF_RRII, bool DPP16 = false> struct WavesPerEU
 // C), so that the next hop of M_pc can take it as chi.
 // FP16 storage in the interleaved layout takes the packed path (pk16.h):
 // neighbour spinors stay packed, half spinors are projected in packed FP16
-// and multiplied with v_dot2_f32_f16 into FP32.
+// and multiplied with v_dot2_f32_f16 into FP32. BF16 storage in that layout
+// projects in FP32 and multiplies with v_dot2_f32_bf16 (no packed BF16 adds
+// on this hardware).
 template <class S, int LAYOUT, bool DAG, bool DPP16, bool MINV, bool CHI = false>
 __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
   typedef typename Store<S>::compute T;
   static_assert(!(DAG && CHI), "the adjoint hop applies A^dag once per site");
   constexpr bool PK = std::is_same<S, _Float16>::value && LAYOUT == QDWF_RIRI;
+  // BF16 storage, interleaved: FP32 spinor arithmetic, SU(3) products as
+  // v_dot2_f32_bf16 on the half spinor rounded to BF16 and the packed links
+  constexpr bool PKB = std::is_same<S, bf16>::value && LAYOUT == QDWF_RIRI;
   constexpr int LSTR = LinkStride<T>::v;
   T* su = reinterpret_cast<T*>(smem);                       // [nsb][8][LSTR]
   int* snb = reinterpret_cast<int*>(su + (size_t)8 * LSTR * k.nsb);   // [8][nsb]
@@ -168,7 +186,7 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
       if (d < 4) { par = p; site = min(cb0 + sl2, Vh - 1); }
       else       { par = q; site = snb[d * k.nsb + sl2]; }
       const S* src = lk + (((long)par * 4 + mu) * Vh + site) * 18;
-      if constexpr (PK) {
+      if constexpr (PK || PKB) {
         const uint32_t* qw = reinterpret_cast<const uint32_t*>(src);
         uint32_t* dstw = reinterpret_cast<uint32_t*>(su + (sl2 * 8 + d) * LSTR);
         uint32_t w[9];
@@ -243,18 +261,8 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
       } else {
         project_pk<MU, SG>(w, h);
       }
-      const uint32_t* lw = reinterpret_cast<const uint32_t*>(lks + D * LSTR);
       uint32_t U[18];
-      {
-        const uint4* q4 = reinterpret_cast<const uint4*>(lw);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const uint4 t4 = q4[j];
-          U[4 * j] = t4.x; U[4 * j + 1] = t4.y; U[4 * j + 2] = t4.z; U[4 * j + 3] = t4.w;
-        }
-        const uint2 t2 = reinterpret_cast<const uint2*>(lw)[8];
-        U[16] = t2.x; U[17] = t2.y;
-      }
+      load_link_words(lks + D * LSTR, U);
       su3_mul_pk<!FWD>(U, U + 9, h, uh);
     } else {
       T* buf = (D & 1) ? vb : va;
@@ -269,10 +277,20 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
         for (int i = 0; i < 24; ++i) w[i] = v[i];
         shift_s<1, 15>(sh, cm, cp, w, v);
       }
-      T h[12], U[18];
-      load_link(lks + D * LSTR, U);
+      T h[12];
       project<MU, SG>(v, h);
-      su3_mul<!FWD>(U, h, uh);
+      if constexpr (PKB) {
+        uint32_t hw[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) hw[i] = pk_bf16(h[2 * i], h[2 * i + 1]);
+        uint32_t U[18];
+        load_link_words(lks + D * LSTR, U);
+        su3_mul_pk<!FWD, true>(U, U + 9, hw, uh);
+      } else {
+        T U[18];
+        load_link(lks + D * LSTR, U);
+        su3_mul<!FWD>(U, h, uh);
+      }
     }
     recon_acc<MU, SG, D == 0>(uh, acc);
   };

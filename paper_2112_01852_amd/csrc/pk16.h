@@ -48,6 +48,19 @@ __device__ inline float dot2(uint32_t a, uint32_t b, float c) {
   return __builtin_amdgcn_fdot2(as_h2(a), as_h2(b), c, false);
 }
 
+// The same with two BF16 products (BF16 storage: the half spinor is
+// projected in FP32 and rounded to BF16 for the products).
+typedef __bf16 bf162v __attribute__((ext_vector_type(2)));
+__device__ inline float dot2_bf16(uint32_t a, uint32_t b, float c) {
+  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf162v, a),
+                                         __builtin_bit_cast(bf162v, b), c, false);
+}
+
+// Two FP32 values rounded to nearest even into one BF16 pair (lo, hi).
+__device__ inline uint32_t pk_bf16(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, (bf162v){(__bf16)lo, (__bf16)hi});
+}
+
 // Two FP32 values rounded to nearest even into one FP16 pair (lo, hi).
 __device__ inline uint32_t pk_f16(float lo, float hi) {
   return as_u32((half2v){(_Float16)lo, (_Float16)hi});
@@ -90,8 +103,9 @@ template <int MU, int SG> __device__ inline void project_pk(const uint32_t* v, u
 
 // u[row][a] = sum_b M[a][b] h[row][b], M = U (DAGL = false) or U^dag, from a
 // link staged as link_words (W0, W1: 9 words each, row-major [a][b]); u in
-// FP32 as (re, im) pairs, the layout su3_mul writes.
-template <bool DAGL>
+// FP32 as (re, im) pairs, the layout su3_mul writes. BF: the words hold BF16
+// pairs (the sign adjustments of link_words are the same bits).
+template <bool DAGL, bool BF = false>
 __device__ inline void su3_mul_pk(const uint32_t* W0, const uint32_t* W1, const uint32_t* h,
                                   float* u) {
 #pragma unroll
@@ -103,8 +117,13 @@ __device__ inline void su3_mul_pk(const uint32_t* W0, const uint32_t* W1, const 
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
         const int e = DAGL ? b * 3 + a : a * 3 + b;
-        re = dot2(W0[e], hh[b], re);
-        im = dot2(W1[e], hh[b], im);
+        if constexpr (BF) {
+          re = dot2_bf16(W0[e], hh[b], re);
+          im = dot2_bf16(W1[e], hh[b], im);
+        } else {
+          re = dot2(W0[e], hh[b], re);
+          im = dot2(W1[e], hh[b], im);
+        }
       }
       u[(r * 3 + a) * 2] = re;
       u[(r * 3 + a) * 2 + 1] = im;
