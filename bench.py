@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 # (profiles/sweep_f32_riri_32x32x32x32x16.md),
 # keyed by the hash of the kernel source they were taken with; any other
 # source reports null until it is profiled again.
-MEASURED_TRAFFIC = {"1f67853a7b43d1f1": 6.576e9}
+MEASURED_TRAFFIC = {"f32855484b1c14ba": 6.581e9}
 FLOPS_PER_SITE = 1320        # Table 3 (real flops per 5D site per hop)
 MOBIUS = dict(M5=1.8, mf=0.01, b=1.5, c=0.5)
 

@@ -1,5 +1,5 @@
-// Bodies of the CG vector kernels (reductions, alpha/beta, the x/p pass of
-// the fused iteration, the reliable-update steps), shared by the launches over one
+// Bodies of the CG vector kernels (reductions, alpha/beta, the direction and
+// x passes of the fused iteration, the reliable-update steps), shared by the launches over one
 // context's right-hand sides (solver.hip) and the grouped launches over many
 // requests (group.hip). Each body does the work of one block `bx` of `NB`
 // for right-hand side `q` (the per-right-hand-side scalar steps take only q);
@@ -167,59 +167,15 @@ __device__ inline void k_beta_body(const double* __restrict__ part, int NB,
   }
 }
 
-// The vector step of the fused iteration, after r and |r|^2 came from the
-// last hop: x += alpha p (if the rhs took this iteration's step) and, while
-// it keeps running, p = r + beta p.
-template <class SX, class SR, class SP>
-__device__ inline void k_update_px_body(SX* __restrict__ x, const SR* __restrict__ r,
-                                        SP* __restrict__ p, long n, long rs,
-                                        const RhsState* __restrict__ st, int vec,
-    int bx, int NB, int q) {
-  typedef typename Store<SR>::compute T;
-  const RhsState& s = st[q];
-  if (!s.xstep) return;
-  const bool run = s.status == ST_RUN;
-  const T al = (T)s.alpha, be = (T)s.beta;
-  SX* xr = x + (long)q * rs;
-  const SR* rr = r + (long)q * rs;
-  SP* pr = p + (long)q * rs;
-  constexpr int E = ChunkWidth<SX, SR, SP>::e;
-  const long nt = vec ? n / TILE : 0;
-  const int lane = threadIdx.x & 63;
-  const long t1 = nt * (bx + 1) / NB;   // this block's contiguous range of tiles
-  for (long t = nt * bx / NB + (threadIdx.x >> 6); t < t1; t += RT / 64) {
-#pragma unroll
-    for (int j = 0; j < 8 / E; ++j) {
-      const long i = t * TILE + j * 64 * E + lane * E;
-      T pv[E], xv[E];
-      Chunk<SP, E>::ld(pr + i, pv);
-      Chunk<SX, E>::ld(xr + i, xv);
-#pragma unroll
-      for (int k = 0; k < E; ++k) xv[k] = xv[k] + al * pv[k];
-      Chunk<SX, E>::st(xr + i, xv);
-      if (run) {
-        T rv[E];
-        Chunk<SR, E>::ld(rr + i, rv);
-#pragma unroll
-        for (int k = 0; k < E; ++k) pv[k] = rv[k] + be * pv[k];
-        Chunk<SP, E>::st(pr + i, pv);
-      }
-    }
-  }
-  for (long i = TILE * nt + (long)bx * RT + threadIdx.x; i < n; i += (long)NB * RT) {
-    const T pv = (T)Store<SP>::to(pr[i]);
-    xr[i] = Store<SX>::from((T)Store<SX>::to(xr[i]) + al * pv);
-    if (run) pr[i] = Store<SP>::from((T)Store<SR>::to(rr[i]) + be * pv);
-  }
-}
-
 // qdwf_solve runs its iterations in groups of up to kGroupSlots and updates
 // x once per group: iteration j of a group reads its search direction from
 // slot j (slot stride ps reals) and writes the next one to slot j + 1; the
 // last adds every step of the group to x and writes the next direction to
 // slot 0, where the next group (and a reliable update) starts.
 // Iteration j < last: slot j+1 = r + beta slot j while the rhs keeps running
-// (one that pauses here keeps its direction in slot j).
+// (one that pauses here keeps its direction in slot j). With ps = 0 and
+// j = 0 it is p = r + beta p in place: the serving pool's p pass, whose x
+// takes each iteration's step in the last hop of M_pc^dag.
 template <class SR, class SP>
 __device__ inline void k_grp_p_body(const SR* __restrict__ r, SP* __restrict__ p0, long ps, int j,
                                     long n, long rs, const RhsState* __restrict__ st, int vec,

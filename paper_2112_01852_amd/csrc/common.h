@@ -257,13 +257,19 @@ struct HopArgs {
   //     (alpha_r = cg_alpha[r * cg_alpha_stride]; cg_r in FP16 for FP16
   //     storage, else in the compute type: double for FP64 storage and
   //     float otherwise; in the output's layout and rhs stride), and the
-  //     sums are of the updated cg_r as stored.
+  //     sums are of the updated cg_r as stored;
+  //   cg = 3: as cg = 2, and cg_x += alpha_r * cg_p at the same sites (the
+  //     iteration's step: cg_p the search direction in the storage type,
+  //     cg_x the inner solution in the compute type; both in the output's
+  //     layout and rhs stride).
   // Rhs whose skip flag is set are left alone.
   int cg;
   void* cg_r;
   const double* cg_alpha;
   int cg_alpha_stride;
   double* cg_site;
+  void* cg_x;
+  const void* cg_p;
 };
 int launch_hop(qdwf_ctx* ctx, int prec, int layout, int dagger, const HopArgs& a,
                hipStream_t st, const HopShape* shape = nullptr);

@@ -147,7 +147,8 @@ g_local(const Table* __restrict__ t, int which, int fp64, int want) {
     const int bx = u - h.start[j];
 
 // The fused iteration's reductions of the per-site sums (|M_pc p|^2, then
-// |r|^2), alpha, beta and the x / p pass, as in the single-context solver.
+// |r|^2), alpha and beta as in the single-context solver, and the p pass
+// (x takes its step in the last hop of M_pc^dag).
 __global__ void __launch_bounds__(RT) g_sum_sites(const Table* __restrict__ t) {
   __shared__ double sh[RT];
   GROUP_LOOP(sites)
@@ -172,13 +173,14 @@ __global__ void __launch_bounds__(RT) g_beta(const Table* __restrict__ t) {
   }
 }
 
-template <class S, class R>
-__global__ void __launch_bounds__(RT) g_update_px(const Table* __restrict__ t) {
+// p = r + beta p in place while the member keeps running (its x took the
+// iteration's step in the last hop of M_pc^dag)
+template <class S>
+__global__ void __launch_bounds__(RT) g_update_p(const Table* __restrict__ t) {
   typedef typename ResidStore<S>::t RR;
   GROUP_LOOP(blas)
-    k_update_px_body<R, RR, S>(reinterpret_cast<R*>(r.xl), reinterpret_cast<const RR*>(r.rl),
-                              reinterpret_cast<S*>(r.p), r.n, r.n, r.st, r.vec_s && r.vec_r, bx,
-                              r.NB, 0);
+    k_grp_p_body<RR, S>(reinterpret_cast<const RR*>(r.rl), reinterpret_cast<S*>(r.p), 0, 0, r.n,
+                        r.n, r.st, r.vec_s && r.vec_r, bx, r.NB, 0);
   }
 }
 
@@ -306,7 +308,7 @@ int record_round(const Table* t, int k, hipStream_t st) {
     mpc_dag(S(), lds_s, loc_s, 0, ST_RUN);
     hipLaunchKernelGGL(g_sum_sites, bg, bb, 0, st, t);
     hipLaunchKernelGGL(g_beta, og, bb, 0, st, t);
-    hipLaunchKernelGGL((g_update_px<S, R>), bg, bb, 0, st, t);
+    hipLaunchKernelGGL((g_update_p<S>), bg, bb, 0, st, t);
   }
   QDWF_HIP(hipGetLastError());
   return QDWF_OK;
@@ -394,11 +396,13 @@ int fill_mdagm(qdwf_ctx* ctx, int prec, const void* in, void* out, void* v, void
     b.beta = be;
     b.chi = dag ? 0 : 1;
     if (cg) {
-      b.cg = dag ? 2 : 1;
+      b.cg = dag ? (cg->x ? 3 : 2) : 1;
       b.cg_r = cg->r;
       b.cg_alpha = cg->alpha;
       b.cg_alpha_stride = cg->alpha_stride;
       b.cg_site = cg->site;
+      b.cg_x = cg->x;
+      b.cg_p = cg->p;
     }
     if ((rc = fill_hop(ctx, prec, b, hk[2 * dag + 1]))) return rc;
   }
@@ -509,7 +513,7 @@ int GroupEngine::set_members(const GroupMember* m, int n, hipStream_t st) {
     GLoc* ls[2] = {&T.loc_s[0][j], &T.loc_s[1][j]};
     const double* alpha = reinterpret_cast<const double*>(reinterpret_cast<const char*>(r.st) +
                                                           offsetof(RhsState, alpha));
-    const CgFuse cg = {0, r.rl, alpha, 0, r.site};
+    const CgFuse cg = {0, r.rl, alpha, 0, r.site, r.xl, r.p};
     if ((rc = fill_mdagm(c, inner_, r.p, r.ap, w + L.off_v, w + L.off_t1, w + L.off_t2, hs, ls, &cg)))
       return rc;
     HopK* hd[4] = {&T.hop_d[0][j], &T.hop_d[1][j], &T.hop_d[2][j], &T.hop_d[3][j]};

@@ -50,6 +50,8 @@ struct HopK {
   const double* cg_alpha;
   int cg_alpha_stride;
   double* cg_site;
+  void* cg_x;          // cg = 3: inner solution, compute type
+  const void* cg_p;    // cg = 3: search direction, storage type
 };
 
 // Target occupancy (waves per SIMD) the register allocator plans for: two for
@@ -352,7 +354,7 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
 #pragma unroll
     for (int i = 0; i < 24; ++i) acc[i] *= hs;
   }
-  if (active && k.cg != 2) {
+  if (active && k.cg < 2) {
     S* out = reinterpret_cast<S*>(k.out[p]) + (long)rc * k.rs_out;
     if constexpr (PK) {
       long i = cbc;
@@ -391,6 +393,17 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
         ss += v * v;
       }
       SiteIO<RS, LAYOUT>::store(rr, cbc, s, Ls, k.plane, rv);
+      if (k.cg == 3) {
+        // the iteration's step at the same sites: x += alpha p
+        T pv[24], xv[24];
+        SiteIO<S, LAYOUT>::load(reinterpret_cast<const S*>(k.cg_p) + (long)rc * k.rs_out, cbc, s,
+                                Ls, k.plane, pv);
+        T* xr = reinterpret_cast<T*>(k.cg_x) + (long)rc * k.rs_out;
+        SiteIO<T, LAYOUT>::load(xr, cbc, s, Ls, k.plane, xv);
+#pragma unroll
+        for (int i = 0; i < 24; ++i) xv[i] = xv[i] + al * pv[i];
+        SiteIO<T, LAYOUT>::store(xr, cbc, s, Ls, k.plane, xv);
+      }
     }
     double* red = reinterpret_cast<double*>(snb + 8 * k.nsb);   // blockDim.x doubles
     red[threadIdx.x] = live ? ss : 0.0;
@@ -436,7 +449,10 @@ int make_hopk(const qdwf_ctx* ctx, int prec, const HopArgs& a, const HopShape& s
   k->cg_alpha = a.cg_alpha;
   k->cg_alpha_stride = a.cg_alpha_stride;
   k->cg_site = a.cg_site;
-  if (a.cg && (a.cg > 2 || !a.epi || a.npar != 1 || !a.cg_site || (a.cg == 2 && (!a.cg_r || !a.cg_alpha))))
+  k->cg_x = a.cg_x;
+  k->cg_p = a.cg_p;
+  if (a.cg && (a.cg > 3 || !a.epi || a.npar != 1 || !a.cg_site ||
+               (a.cg >= 2 && (!a.cg_r || !a.cg_alpha)) || (a.cg == 3 && (!a.cg_x || !a.cg_p))))
     return fail(QDWF_EINVAL, "fused CG step needs a one-parity hop with epilogue and its buffers");
   k->minv = MINV;
   if (MINV) {

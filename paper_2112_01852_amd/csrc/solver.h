@@ -30,13 +30,15 @@ struct RhsState {
 };
 
 // The CG step a solver iteration fuses into the epilogue hop of M_pc or
-// M_pc^dag (HopArgs::cg and the fields after it).
+// M_pc^dag (HopArgs::cg and the fields after it; x and p only for cg = 3).
 struct CgFuse {
   int mode;
   void* r;
   const double* alpha;
   int alpha_stride;
   double* site;
+  void* x;
+  const void* p;
 };
 
 inline size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }

@@ -266,6 +266,8 @@ int apply_mpc(qdwf_ctx* ctx, int prec, int layout, int dagger, void* out, const 
     a.cg_alpha = cg->alpha;
     a.cg_alpha_stride = cg->alpha_stride;
     a.cg_site = cg->site;
+    a.cg_x = cg->x;
+    a.cg_p = cg->p;
   }
   return launch_hop(ctx, prec, layout, dagger, a, st);
 }
