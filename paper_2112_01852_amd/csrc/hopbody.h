@@ -369,16 +369,29 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
     }
   }
   if (!MINV && k.cg) {
-    // the CG step: this 5D site's sum of squares (in FP64, components in
-    // order), then each checkerboard site's sum over its slices in slice
-    // order, so the per-site values do not depend on the launch shape
+    // the CG step: this 5D site's sum of squares (components in order), then
+    // each checkerboard site's sum over its slices in slice order (FP64), so
+    // the per-site values do not depend on the launch shape. The site's sum
+    // is taken in FP32 where the values are 16-bit numbers as stored (their
+    // squares are exact in FP32, and 24 of them add with a relative error
+    // below 2^-19), in FP64 otherwise.
     const bool live = active && (!k.skip || k.skip[(long)rc * k.skip_stride] == 0);
     double ss = 0.0;
     if (k.cg == 1) {
+      if constexpr (sizeof(S) == 2) {
+        float s32 = 0.0f;
 #pragma unroll
-      for (int i = 0; i < 24; ++i) {
-        const double v = (double)Store<S>::to(Store<S>::from(acc[i]));   // as stored
-        ss += v * v;
+        for (int i = 0; i < 24; ++i) {
+          const float v = (float)Store<S>::to(Store<S>::from(acc[i]));   // as stored
+          s32 = __builtin_fmaf(v, v, s32);
+        }
+        ss = (double)s32;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 24; ++i) {
+          const double v = (double)Store<S>::to(Store<S>::from(acc[i]));   // as stored
+          ss += v * v;
+        }
       }
     } else if (live) {
       typedef typename ResidStore<S>::t RS;
@@ -386,11 +399,22 @@ __device__ inline void hop_block(const HopK& k, int L, unsigned char* smem) {
       T rv[24];
       SiteIO<RS, LAYOUT>::load(rr, cbc, s, Ls, k.plane, rv);
       const T al = (T)k.cg_alpha[(long)rc * k.cg_alpha_stride];
+      if constexpr (sizeof(RS) == 2) {
+        float s32 = 0.0f;
 #pragma unroll
-      for (int i = 0; i < 24; ++i) {
-        rv[i] = rv[i] - al * acc[i];
-        const double v = (double)Store<RS>::to(Store<RS>::from(rv[i]));   // as stored
-        ss += v * v;
+        for (int i = 0; i < 24; ++i) {
+          rv[i] = rv[i] - al * acc[i];
+          const float v = (float)Store<RS>::to(Store<RS>::from(rv[i]));   // as stored
+          s32 = __builtin_fmaf(v, v, s32);
+        }
+        ss = (double)s32;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 24; ++i) {
+          rv[i] = rv[i] - al * acc[i];
+          const double v = (double)Store<RS>::to(Store<RS>::from(rv[i]));   // as stored
+          ss += v * v;
+        }
       }
       SiteIO<RS, LAYOUT>::store(rr, cbc, s, Ls, k.plane, rv);
       if (k.cg == 3) {
