@@ -61,14 +61,41 @@ def test_checker_catches_a_hazard():
         _groups(["v_add_f32_e32 v20, v2, v3", "v_fmac_f32_dpp v10, v20, v1 row_ror:1"])
 
 
+_ASM = {}
+
+
+def _asm(tmp_path_factory, src):
+    """The gfx950 assembly of one source, built with the library's device
+    flags (compiled once per test session)."""
+    if src not in _ASM:
+        out = tmp_path_factory.mktemp("asm") / (src + ".s")
+        cmd = [_hipcc(), "-x", "hip", f"--offload-arch={B.ARCH}", "-O3", "-std=c++17",
+               "-I", B.INCLUDE, "-I", B.CSRC, *B.DEVICE_FLAGS, "--cuda-device-only", "-S",
+               os.path.join(B.CSRC, src), "-o", str(out)]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr[-2000:]
+        _ASM[src] = [l.strip() for l in out.read_text().splitlines()]
+    return _ASM[src]
+
+
 @pytest.mark.skipif(_hipcc() is None, reason="hipcc not available")
 @pytest.mark.parametrize("src", ["sweep.hip", "hop.hip"])
-def test_grouped_dpp_fmas_read_no_register_written_in_their_group(tmp_path, src):
-    out = tmp_path / (src + ".s")
-    cmd = [_hipcc(), "-x", "hip", f"--offload-arch={B.ARCH}", "-O3", "-std=c++17",
-           "-I", B.INCLUDE, "-I", B.CSRC, *B.DEVICE_FLAGS, "--cuda-device-only", "-S",
-           os.path.join(B.CSRC, src), "-o", str(out)]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    assert r.returncode == 0, r.stderr[-2000:]
-    lines = [l.strip() for l in out.read_text().splitlines()]
-    assert _groups(lines) > 0
+def test_grouped_dpp_fmas_read_no_register_written_in_their_group(tmp_path_factory, src):
+    assert _groups(_asm(tmp_path_factory, src)) > 0
+
+
+@pytest.mark.skipif(_hipcc() is None, reason="hipcc not available")
+@pytest.mark.parametrize("src", ["sweep.hip", "hop.hip", "group.hip"])
+def test_no_packed_fp32_and_no_accumulating_dot2(tmp_path_factory, src):
+    """The device flags keep packed-FP32 arithmetic out of every kernel and
+    select the three-operand dot products: no v_pk_{add,mul,fma}_f32 and no
+    two-operand v_dot2c_f32_{f16,bf16} in the hop kernels' code, while the
+    16-bit paths do use v_dot2_f32_f16 / v_dot2_f32_bf16."""
+    lines = _asm(tmp_path_factory, src)
+    ops = [l.split()[0] for l in lines if l.startswith("v_")]
+    bad = sorted({o for o in ops if re.match(r"v_pk_(add|mul|fma)_f32", o)})
+    assert not bad, bad
+    acc = sorted({o for o in ops if o.startswith("v_dot2c_f32_")})
+    assert not acc, acc
+    if src != "sweep.hip":
+        assert "v_dot2_f32_f16" in ops and "v_dot2_f32_bf16" in ops
