@@ -13,6 +13,9 @@
 //     link is staged in the two sign-adjusted forms its direction needs, so
 //     every product is a plain dot2;
 //   * reconstruction and every later step stay in FP32.
+// BF16 storage uses only the SU(3) part: its half spinor is projected in
+// FP32 (there are no packed BF16 adds) and rounded to BF16 for
+// v_dot2_f32_bf16 against links staged the same way.
 // Everything is written with vector types and builtins, so the compiler sees
 // the DOT instructions and inserts the wait states their results need before
 // other VALU instructions read them.
